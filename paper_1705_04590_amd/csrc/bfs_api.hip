@@ -1,0 +1,508 @@
+// Host controller and C ABI of libbfs (see include/bfs.h).
+//
+// The level loop is driven from the host: after every level it copies three
+// device counters (next-frontier size, its edge count, entries examined) into
+// pinned host memory, and applies the direction rule of Section 4.4 before
+// launching the next level: top-down while the frontier's edges m_f stay at
+// or below the unexplored edges m_u divided by alpha, bottom-up until the
+// frontier shrinks below n / beta.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bfs.h"
+#include "bfs_internal.h"
+
+using namespace bfsk;
+
+namespace {
+
+thread_local std::string g_err;
+
+bfs_status fail(bfs_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return fail(BFS_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+enum GraphKind { KIND_CSR = 1, KIND_DCSC = 2 };
+
+}  // namespace
+
+struct bfs_graph {
+    int kind = 0;
+    int device = 0;
+    uint32_t flags = 0;
+    // CSR
+    int64_t n = 0, nnz = 0;
+    int off_bytes = 8;
+    const void* off = nullptr;
+    const int32_t* cols = nullptr;
+    // DCSC block
+    int64_t nrows = 0, ncols = 0, row_base = 0, col_base = 0, nzc = 0, nzr = 0;
+    const int32_t *jc = nullptr, *ir = nullptr, *jr = nullptr, *ic = nullptr;
+    const int64_t *cp = nullptr, *rp = nullptr;
+    // host metadata
+    uint64_t* h_buf = nullptr;              // pinned: counter readback
+    std::vector<hipEvent_t> events;         // timing pool
+};
+
+namespace {
+
+// -------------------------------------------------------------- workspace layout
+struct SingleLayout {
+    size_t counters, visited, fbits, nbits, claim, q0, q1, scan, tiles, partial, total;
+};
+
+SingleLayout single_layout(const bfs_graph* g) {
+    SingleLayout L{};
+    const int64_t n = g->n;
+    const int64_t W = (n + 63) / 64;
+    const int64_t ntiles = (g->nnz + TD_TILE - 1) / TD_TILE;
+    size_t o = 0;
+    L.counters = o; o = align_up(o + sizeof(uint64_t) * SLOTS * SLOT_WORDS);
+    L.visited = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
+    L.fbits = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
+    L.nbits = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
+    L.claim = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
+    L.q0 = o; o = align_up(o + sizeof(int32_t) * (size_t)(n + 1));
+    L.q1 = o; o = align_up(o + sizeof(int32_t) * (size_t)(n + 1));
+    L.scan = o; o = align_up(o + sizeof(int64_t) * (size_t)(n + 2));
+    L.tiles = o; o = align_up(o + sizeof(int32_t) * (size_t)(ntiles + 2));
+    L.partial = o; o = align_up(o + sizeof(int64_t) * (size_t)((n + SCAN_TILE - 1) / SCAN_TILE + 2));
+    L.total = o;
+    return L;
+}
+
+// -------------------------------------------------------------- timing
+struct Timer {
+    bfs_graph* g;
+    hipStream_t s;
+    bool on;
+    struct Rec { int kind; int level; size_t ev; };
+    std::vector<Rec> recs;
+    size_t used = 0;
+
+    hipError_t ensure(size_t k) {
+        while (g->events.size() < k) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            g->events.push_back(e);
+        }
+        return hipSuccess;
+    }
+    // brackets one launch (or a few launches of one kind)
+    hipError_t begin() {
+        if (!on) return hipSuccess;
+        hipError_t r = ensure(used + 2);
+        if (r != hipSuccess) return r;
+        return hipEventRecord(g->events[used], s);
+    }
+    hipError_t end(int kind, int level) {
+        if (!on) return hipSuccess;
+        hipError_t r = hipEventRecord(g->events[used + 1], s);
+        recs.push_back({kind, level, used});
+        used += 2;
+        return r;
+    }
+    void collect(bfs_stats* st) {
+        for (auto& r : recs) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, g->events[r.ev], g->events[r.ev + 1]) != hipSuccess) ms = 0.f;
+            st->kernel_ms[r.kind] += ms;
+            if (r.level >= 0 && r.level < BFS_STATS_MAX_LEVELS &&
+                (r.kind == BFS_K_TD_EXPAND || r.kind == BFS_K_BU_SWEEP || r.kind == BFS_K_MS_LEVEL))
+                st->level_ms[r.level] += ms;
+        }
+    }
+};
+
+bfs_status check_csr_graph(const bfs_graph* g) {
+    if (!g || g->kind != KIND_CSR) return fail(BFS_E_INVALID_ARG, "graph handle is not a CSR graph");
+    return BFS_OK;
+}
+
+template <typename OffT>
+bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* parent, int32_t* depth, char* ws,
+                      hipStream_t stream, bfs_stats* st) {
+    const auto t_start = std::chrono::steady_clock::now();
+    const OffT* off = (const OffT*)g->off;
+    const int64_t n = g->n, W = (n + 63) / 64;
+    const SingleLayout Lo = single_layout(g);
+    uint64_t* counters = (uint64_t*)(ws + Lo.counters);
+    uint64_t* visited = (uint64_t*)(ws + Lo.visited);
+    uint64_t* fbits = (uint64_t*)(ws + Lo.fbits);
+    uint64_t* nbits = (uint64_t*)(ws + Lo.nbits);
+    uint64_t* claim = (uint64_t*)(ws + Lo.claim);
+    int32_t* qcur = (int32_t*)(ws + Lo.q0);
+    int32_t* qnext = (int32_t*)(ws + Lo.q1);
+    int64_t* scan = (int64_t*)(ws + Lo.scan);
+    int32_t* tiles = (int32_t*)(ws + Lo.tiles);
+    int64_t* partial = (int64_t*)(ws + Lo.partial);
+    const bool min_mode = o.parent_mode == BFS_PARENT_MIN;
+    const int serial = o.bu_serial > 0 ? o.bu_serial : 16;
+    Launch L{stream, o.grid_blocks > 0 ? o.grid_blocks : 2048};
+    Timer T{g, stream, o.timing != 0, {}, 0};
+
+    // degree of the source: the first frontier's edge count
+    uint64_t* h = g->h_buf;
+    OffT* hoff = (OffT*)h;
+    HIP_TRY(hipMemcpyAsync(hoff, (const char*)g->off + sizeof(OffT) * src, 2 * sizeof(OffT), hipMemcpyDeviceToHost,
+                           stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    const int64_t deg_s = (int64_t)hoff[1] - (int64_t)hoff[0];
+
+    HIP_TRY(T.begin());
+    launch_init(L, parent, depth, n, visited, fbits, claim, W, qcur, src, counters);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(T.end(BFS_K_INIT, -1));
+    if (st) st->launches[BFS_K_INIT] += 1;
+
+    int64_t n_f = 1, m_f = deg_s, m_u = g->nnz - deg_s, qlen = deg_s > 0 ? 1 : 0;
+    int64_t unvisited = n - 1;
+    int cur_dir = (o.dir == BFS_DIR_BU) ? 1 : 0;
+    bool fmt_queue = true;       // frontier held as queue (true) or bitmap fbits (false)
+    bool fbits_fresh = true;     // fbits holds exactly the frontier (init sets {src})
+    int level = 0;
+    int64_t reached = 1, examined = 0;
+    for (;;) {
+        // ---- direction for this level (Section 4.4)
+        if (o.dir == BFS_DIR_TD) cur_dir = 0;
+        else if (o.dir == BFS_DIR_BU) cur_dir = 1;
+        else if (cur_dir == 0) { if ((double)m_f * o.alpha > (double)m_u) cur_dir = 1; }
+        else { if ((double)n_f * o.beta < (double)n) cur_dir = 0; }
+
+        uint64_t* slot = counters + (size_t)(level % SLOTS) * SLOT_WORDS;
+        uint64_t* zslot = counters + (size_t)((level + 1) % SLOTS) * SLOT_WORDS;
+        if (cur_dir == 1 && fmt_queue) {
+            if (!fbits_fresh) {
+                HIP_TRY(T.begin());
+                launch_clear_words(L, fbits, W);
+                launch_queue_to_bitmap(L, qcur, qlen, fbits);
+                HIP_TRY(hipGetLastError());
+                HIP_TRY(T.end(BFS_K_CONVERT, level));
+                if (st) st->launches[BFS_K_CONVERT] += 2;
+            }
+            fmt_queue = false;
+        } else if (cur_dir == 0 && !fmt_queue) {
+            // the bitmap -> queue conversion counts into this level's slot
+            HIP_TRY(T.begin());
+            launch_bitmap_to_queue(L, fbits, W, qcur, slot + S_EXAMINED + 1);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(T.end(BFS_K_CONVERT, level));
+            if (st) st->launches[BFS_K_CONVERT] += 1;
+            HIP_TRY(hipMemcpyAsync(h, slot + S_EXAMINED + 1, sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            qlen = (int64_t)h[0];
+            fmt_queue = true;
+        }
+
+        const int32_t next_depth = level + 1;
+        if (cur_dir == 0) {
+            if (m_f > 0 && qlen > 0) {
+                HIP_TRY(T.begin());
+                int nl = launch_td_scan<OffT>(L, off, qcur, qlen, m_f, scan, tiles, partial);
+                HIP_TRY(hipGetLastError());
+                HIP_TRY(T.end(BFS_K_TD_SCAN, level));
+                HIP_TRY(T.begin());
+                launch_td_expand<OffT>(L, min_mode, off, g->cols, g->nnz, qcur, qlen, scan, tiles, m_f, parent,
+                                       depth, visited, claim, qnext, slot, zslot, next_depth);
+                HIP_TRY(hipGetLastError());
+                HIP_TRY(T.end(BFS_K_TD_EXPAND, level));
+                if (min_mode) {
+                    HIP_TRY(T.begin());
+                    launch_merge_claim(L, visited, claim, W);
+                    HIP_TRY(hipGetLastError());
+                    HIP_TRY(T.end(BFS_K_CONVERT, level));
+                }
+                if (st) {
+                    st->launches[BFS_K_TD_SCAN] += nl;
+                    st->launches[BFS_K_TD_EXPAND] += 1;
+                    if (min_mode) st->launches[BFS_K_CONVERT] += 1;
+                }
+            } else {
+                // nothing to expand: this level's slot stays zero -> search ends
+                HIP_TRY(T.begin());
+                launch_clear_words(L, slot, SLOT_WORDS);
+                HIP_TRY(hipGetLastError());
+                HIP_TRY(T.end(BFS_K_CONVERT, level));
+            }
+        } else {
+            HIP_TRY(T.begin());
+            launch_bu_sweep<OffT>(L, off, g->cols, fbits, nbits, visited, parent, depth, n, W, next_depth, serial,
+                                  slot, zslot);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(T.end(BFS_K_BU_SWEEP, level));
+            if (st) st->launches[BFS_K_BU_SWEEP] += 1;
+        }
+        HIP_TRY(hipMemcpyAsync(h, slot, sizeof(uint64_t) * SLOT_WORDS, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        const int64_t n_next = (int64_t)h[S_NNEXT];
+        const int64_t m_next = (int64_t)h[S_MNEXT];
+        const int64_t lvl_examined = cur_dir == 0 ? m_f : (int64_t)h[S_EXAMINED];
+        examined += lvl_examined;
+        if (st && level < BFS_STATS_MAX_LEVELS) {
+            st->level_dir[level] = (int8_t)cur_dir;
+            st->level_nf[level] = n_f;
+            st->level_mf[level] = m_f;
+            st->level_mu[level] = m_u;
+            st->level_unvisited[level] = unvisited;
+            st->level_examined[level] = lvl_examined;
+        }
+        if (st) {
+            if (cur_dir == 0) st->td_levels++; else st->bu_levels++;
+        }
+        ++level;
+        if (n_next == 0) break;
+        reached += n_next;
+        unvisited -= n_next;
+        m_u -= m_next;
+        n_f = n_next;
+        m_f = m_next;
+        if (cur_dir == 0) {
+            qlen = (int64_t)h[S_QLEN];
+            int32_t* t = qcur; qcur = qnext; qnext = t;
+            fbits_fresh = false;
+        } else {
+            uint64_t* t = fbits; fbits = nbits; nbits = t;
+            fbits_fresh = true;
+        }
+        if (level > n + 1) return fail(BFS_E_HIP, "level loop did not terminate");
+    }
+    if (st) {
+        st->levels = level;
+        st->reached = reached;
+        st->edges_examined = examined;
+        if (T.on) {
+            HIP_TRY(hipStreamSynchronize(stream));
+            T.collect(st);
+        }
+        st->total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    return BFS_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+void bfs_opts_default(bfs_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->dir = BFS_DIR_DO;
+    o->parent_mode = BFS_PARENT_ANY;
+    o->alpha = 15.0;
+    o->beta = 18.0;
+}
+
+const char* bfs_last_error(void) { return g_err.c_str(); }
+
+const char* bfs_status_string(bfs_status s) {
+    switch (s) {
+        case BFS_OK: return "ok";
+        case BFS_E_INVALID_ARG: return "invalid argument";
+        case BFS_E_OUT_OF_RANGE: return "id out of range";
+        case BFS_E_UNSORTED: return "rows not sorted";
+        case BFS_E_NOT_SYMMETRIC: return "graph not symmetric";
+        case BFS_E_NO_MEMORY: return "out of host memory";
+        case BFS_E_HIP: return "HIP runtime error";
+        case BFS_E_BUDGET: return "workspace too small";
+        case BFS_E_UNSUPPORTED: return "unsupported for this graph or mode";
+    }
+    return "unknown status";
+}
+
+bfs_status bfs_create_graph_csr(int64_t n, const void* d_offsets, int offset_bytes, const int32_t* d_cols,
+                                int64_t nnz, uint32_t flags, void* hip_stream, bfs_graph** out) {
+    if (!out) return fail(BFS_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 0 || n > 2147483647LL) return fail(BFS_E_INVALID_ARG, "n=%lld outside [0, 2^31-1]", (long long)n);
+    if (nnz < 0) return fail(BFS_E_INVALID_ARG, "nnz < 0");
+    if (offset_bytes != 4 && offset_bytes != 8) return fail(BFS_E_INVALID_ARG, "offset_bytes must be 4 or 8");
+    if (offset_bytes == 4 && nnz > 2147483647LL) return fail(BFS_E_INVALID_ARG, "nnz needs int64 offsets");
+    if (!d_offsets) return fail(BFS_E_INVALID_ARG, "offsets is NULL");
+    if (nnz > 0 && !d_cols) return fail(BFS_E_INVALID_ARG, "cols is NULL");
+    if (flags & ~(BFS_GRAPH_SYMMETRIC | BFS_GRAPH_SORTED | BFS_GRAPH_VALIDATE))
+        return fail(BFS_E_INVALID_ARG, "unknown flag bits 0x%x", flags);
+    bfs_graph* g = new (std::nothrow) bfs_graph();
+    if (!g) return fail(BFS_E_NO_MEMORY, "graph handle");
+    g->kind = KIND_CSR;
+    g->n = n;
+    g->nnz = nnz;
+    g->off_bytes = offset_bytes;
+    g->off = d_offsets;
+    g->cols = d_cols;
+    g->flags = flags & (BFS_GRAPH_SYMMETRIC | BFS_GRAPH_SORTED);
+    hipError_t e = hipGetDevice(&g->device);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&g->h_buf, 4096, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete g;
+        return fail(BFS_E_HIP, "create: %s", hipGetErrorString(e));
+    }
+    if ((flags & BFS_GRAPH_VALIDATE) && n > 0) {
+        hipStream_t s = (hipStream_t)hip_stream;
+        uint32_t* d_err = nullptr;
+        e = hipMalloc((void**)&d_err, sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMemsetAsync(d_err, 0, sizeof(uint32_t), s);
+        if (e == hipSuccess) {
+            Launch L{s, 4096};
+            if (offset_bytes == 4)
+                launch_validate_csr<int32_t>(L, (const int32_t*)d_offsets, d_cols, n, nnz, g->flags, d_err);
+            else
+                launch_validate_csr<int64_t>(L, (const int64_t*)d_offsets, d_cols, n, nnz, g->flags, d_err);
+            e = hipGetLastError();
+        }
+        uint32_t herr = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&herr, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(s);
+        if (d_err) (void)hipFree(d_err);
+        if (e != hipSuccess) {
+            bfs_destroy_graph(g);
+            return fail(BFS_E_HIP, "validation: %s", hipGetErrorString(e));
+        }
+        bfs_status bad = BFS_OK;
+        if (herr & VE_OFFSETS) bad = fail(BFS_E_INVALID_ARG, "offsets not monotone or not ending at nnz");
+        else if (herr & VE_RANGE) bad = fail(BFS_E_OUT_OF_RANGE, "column id outside [0, n)");
+        else if (herr & VE_UNSORTED) bad = fail(BFS_E_UNSORTED, "a row is not ascending");
+        else if (herr & VE_ASYM) bad = fail(BFS_E_NOT_SYMMETRIC, "an entry (u,v) has no (v,u)");
+        if (bad != BFS_OK) {
+            bfs_destroy_graph(g);
+            return bad;
+        }
+    }
+    *out = g;
+    return BFS_OK;
+}
+
+bfs_status bfs_create_graph_dcsc(int64_t nrows, int64_t ncols, int64_t row_base, int64_t col_base, int64_t nzc,
+                                 const int32_t* d_jc, const int64_t* d_cp, const int32_t* d_ir, int64_t nzr,
+                                 const int32_t* d_jr, const int64_t* d_rp, const int32_t* d_ic, int64_t nnz,
+                                 uint32_t flags, void* hip_stream, bfs_graph** out) {
+    (void)hip_stream;
+    if (!out) return fail(BFS_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (nrows < 1 || ncols < 1 || nrows > 2147483647LL || ncols > 2147483647LL)
+        return fail(BFS_E_INVALID_ARG, "block shape %lld x %lld", (long long)nrows, (long long)ncols);
+    if (row_base < 0 || col_base < 0 || col_base + ncols > 2147483648LL)
+        return fail(BFS_E_INVALID_ARG, "block base out of range");
+    if (nzc < 0 || nzc > ncols || nnz < 0 || (nnz > 0 && (!d_jc || !d_cp || !d_ir)) || !d_cp)
+        return fail(BFS_E_INVALID_ARG, "bad DCSC arrays");
+    if (d_jr && (nzr < 0 || nzr > nrows || !d_rp || (nnz > 0 && !d_ic)))
+        return fail(BFS_E_INVALID_ARG, "bad row-major arrays");
+    bfs_graph* g = new (std::nothrow) bfs_graph();
+    if (!g) return fail(BFS_E_NO_MEMORY, "graph handle");
+    g->kind = KIND_DCSC;
+    g->nrows = nrows; g->ncols = ncols; g->row_base = row_base; g->col_base = col_base;
+    g->nzc = nzc; g->jc = d_jc; g->cp = d_cp; g->ir = d_ir;
+    g->nzr = d_jr ? nzr : 0; g->jr = d_jr; g->rp = d_rp; g->ic = d_ic;
+    g->nnz = nnz;
+    g->flags = flags & (BFS_GRAPH_SYMMETRIC | BFS_GRAPH_SORTED);
+    hipError_t e = hipGetDevice(&g->device);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&g->h_buf, 4096, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete g;
+        return fail(BFS_E_HIP, "create: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return BFS_OK;
+}
+
+void bfs_destroy_graph(bfs_graph* g) {
+    if (!g) return;
+    for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
+    if (g->h_buf) (void)hipHostFree(g->h_buf);
+    delete g;
+}
+
+size_t bfs_workspace_bytes(const bfs_graph* g, int k) {
+    if (!g) return 0;
+    if (g->kind == KIND_CSR) {
+        if (k < 1 || k > 64) return 0;
+        if (k == 1) return single_layout(g).total;
+        return 0;
+    }
+    return 0;
+}
+
+bfs_status bfs_run(bfs_graph* g, int64_t source, const bfs_opts* opts, int32_t* d_parent, int32_t* d_depth,
+                   void* d_workspace, size_t workspace_bytes, void* hip_stream, bfs_stats* stats) {
+    bfs_status s = check_csr_graph(g);
+    if (s != BFS_OK) return s;
+    bfs_opts o;
+    bfs_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.dir < BFS_DIR_DO || o.dir > BFS_DIR_BU) return fail(BFS_E_INVALID_ARG, "bad dir %d", o.dir);
+    if (o.parent_mode != BFS_PARENT_ANY && o.parent_mode != BFS_PARENT_MIN)
+        return fail(BFS_E_INVALID_ARG, "bad parent_mode %d", o.parent_mode);
+    if (!(o.alpha > 0) || !(o.beta > 0)) return fail(BFS_E_INVALID_ARG, "alpha and beta must be > 0");
+    if (source < 0 || source >= g->n)
+        return fail(BFS_E_OUT_OF_RANGE, "source %lld outside [0, %lld)", (long long)source, (long long)g->n);
+    if (!d_parent || !d_depth || !d_workspace) return fail(BFS_E_INVALID_ARG, "NULL output or workspace");
+    if ((uintptr_t)d_workspace % ALIGN) return fail(BFS_E_INVALID_ARG, "workspace not 256-byte aligned");
+    if (workspace_bytes < single_layout(g).total)
+        return fail(BFS_E_BUDGET, "workspace %zu < %zu bytes", workspace_bytes, single_layout(g).total);
+    if (o.dir != BFS_DIR_TD && !(g->flags & BFS_GRAPH_SYMMETRIC))
+        return fail(BFS_E_UNSUPPORTED, "bottom-up levels need a graph created with BFS_GRAPH_SYMMETRIC");
+    if (o.dir != BFS_DIR_TD && o.parent_mode == BFS_PARENT_MIN && !(g->flags & BFS_GRAPH_SORTED))
+        return fail(BFS_E_UNSUPPORTED, "minimum parents with bottom-up levels need BFS_GRAPH_SORTED");
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev != g->device) {
+        if (hipSetDevice(g->device) != hipSuccess) return fail(BFS_E_HIP, "hipSetDevice(%d) failed", g->device);
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (g->off_bytes == 4)
+        s = run_single<int32_t>(g, source, o, d_parent, d_depth, (char*)d_workspace, st, stats);
+    else
+        s = run_single<int64_t>(g, source, o, d_parent, d_depth, (char*)d_workspace, st, stats);
+    if (dev != g->device) (void)hipSetDevice(dev);
+    return s;
+}
+
+bfs_status bfs_run_multi(bfs_graph* g, const int64_t* h_sources, int k, const bfs_opts* opts, int32_t* d_parent,
+                         int32_t* d_depth, void* d_workspace, size_t workspace_bytes, void* hip_stream,
+                         bfs_stats* stats) {
+    (void)g; (void)h_sources; (void)k; (void)opts; (void)d_parent; (void)d_depth; (void)d_workspace;
+    (void)workspace_bytes; (void)hip_stream; (void)stats;
+    return fail(BFS_E_UNSUPPORTED, "bfs_run_multi is not built yet");
+}
+
+bfs_status bfs_block_td(bfs_graph* g, const int32_t* d_frontier, int64_t nf, int32_t* d_out_rows,
+                        int32_t* d_out_parents, int64_t* d_nout, void* d_workspace, size_t workspace_bytes,
+                        void* hip_stream) {
+    (void)g; (void)d_frontier; (void)nf; (void)d_out_rows; (void)d_out_parents; (void)d_nout; (void)d_workspace;
+    (void)workspace_bytes; (void)hip_stream;
+    return fail(BFS_E_UNSUPPORTED, "bfs_block_td is not built yet");
+}
+
+bfs_status bfs_block_bu(bfs_graph* g, const uint64_t* d_fbits, uint64_t* d_completed, int64_t row_lo,
+                        int64_t row_hi, int32_t* d_out_rows, int32_t* d_out_parents, int64_t* d_nout,
+                        void* d_workspace, size_t workspace_bytes, void* hip_stream) {
+    (void)g; (void)d_fbits; (void)d_completed; (void)row_lo; (void)row_hi; (void)d_out_rows; (void)d_out_parents;
+    (void)d_nout; (void)d_workspace; (void)workspace_bytes; (void)hip_stream;
+    return fail(BFS_E_UNSUPPORTED, "bfs_block_bu is not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// Internal interface between the host controller (bfs_api.hip) and the
+// gfx950 kernels (bfs_kernels.hip, bfs_multi.hip, bfs_block.hip).  Not part
+// of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bfsk {
+
+constexpr int WAVE = 64;
+constexpr int TD_BLOCK = 256;                 // threads per top-down expand workgroup
+constexpr int TD_EPT = 4;                     // edges per thread per tile
+constexpr int TD_TILE = TD_BLOCK * TD_EPT;    // edges per tile
+constexpr int SCAN_BLOCK = 1024;              // threads per scan workgroup
+constexpr int SCAN_IPT = 4;                   // items per scan thread
+constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_IPT;
+constexpr int BU_BLOCK = 256;                 // 4 waves, one 64-vertex word per wave
+
+// Per-level counter slot (uint64 words).  A ring of SLOTS slots lets level
+// d write slot d % SLOTS while any kernel of level d clears slot (d+1) % SLOTS.
+enum { S_QLEN = 0, S_NNEXT = 1, S_MNEXT = 2, S_EXAMINED = 3, SLOT_WORDS = 8, SLOTS = 3 };
+
+// Validation error bits.
+enum { VE_OFFSETS = 1, VE_RANGE = 2, VE_UNSORTED = 4, VE_ASYM = 8 };
+
+struct Launch {
+    hipStream_t stream;
+    int grid_cap;   // workgroup cap for grid-stride kernels
+};
+
+// ---- single source -------------------------------------------------------
+void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, uint64_t* visited, uint64_t* fbits,
+                 uint64_t* claim, int64_t W, int32_t* queue, int64_t src, uint64_t* counters);
+
+// degree prefix sum of the frontier queue + tile partition for the expand
+// (scan[i] = sum of degrees of q[0..i), tile_start[t] = queue index owning
+// edge t*TD_TILE, tile_start[ntiles] = qlen-1).  partial needs
+// ceil(qlen/SCAN_TILE)+1 int64.
+template <typename OffT>
+int launch_td_scan(const Launch& L, const OffT* off, const int32_t* q, int64_t qlen, int64_t total, int64_t* scan,
+                   int32_t* tile_start, int64_t* partial);
+
+template <typename OffT>
+void launch_td_expand(const Launch& L, bool min_mode, const OffT* off, const int32_t* cols, int64_t nnz,
+                      const int32_t* q, int64_t qlen, const int64_t* scan, const int32_t* tile_start, int64_t total,
+                      int32_t* parent, int32_t* depth, uint64_t* visited, uint64_t* claim, int32_t* qnext,
+                      uint64_t* slot, uint64_t* zslot, int32_t next_depth);
+
+template <typename OffT>
+void launch_bu_sweep(const Launch& L, const OffT* off, const int32_t* cols, const uint64_t* fbits, uint64_t* nbits,
+                     uint64_t* visited, int32_t* parent, int32_t* depth, int64_t n, int64_t W, int32_t next_depth,
+                     int serial_len, uint64_t* slot, uint64_t* zslot);
+
+void launch_clear_words(const Launch& L, uint64_t* w, int64_t nw);
+void launch_queue_to_bitmap(const Launch& L, const int32_t* q, int64_t qlen, uint64_t* bits);
+void launch_bitmap_to_queue(const Launch& L, const uint64_t* bits, int64_t W, int32_t* q, uint64_t* qlen_ctr);
+void launch_merge_claim(const Launch& L, uint64_t* visited, uint64_t* claim, int64_t W);
+
+template <typename OffT>
+void launch_validate_csr(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, int64_t nnz,
+                         uint32_t flags, uint32_t* err);
+
+}  // namespace bfsk

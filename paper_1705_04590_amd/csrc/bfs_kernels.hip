@@ -1,0 +1,549 @@
+// Single-source direction-optimizing BFS kernels for gfx950 (wave64).
+//
+// Top-down level (Alg. 1; the local discovery + local update of Alg. 3):
+//   a degree prefix sum over the frontier queue assigns every adjacency entry
+//   of the frontier a global index; fixed tiles of TD_TILE entries are then
+//   expanded by workgroups, each tile's frontier vertices staged in LDS, so a
+//   hub's row is spread over many workgroups.  A child is claimed with an
+//   atomic compare-and-swap on parent[] (ANY) or by atomicMin on parent[]
+//   plus an atomicOr claim bit (MIN, the (select2nd, min) semiring of
+//   Section 4.2).  Winners are compacted in LDS (wave ballot + mbcnt, one
+//   LDS atomic per wave) and appended to the next queue with one global
+//   atomicAdd per tile.
+// Bottom-up level (Alg. 2; the local discovery of Alg. 4):
+//   one wave owns 64 consecutive vertices = one word of the visited bitmap.
+//   Fully visited words are skipped.  Each unvisited lane scans its sorted
+//   row serially for up to `serial_len` entries probing the frontier bitmap;
+//   rows still unresolved are then scanned by the whole wave 64 entries at a
+//   time, keeping the first hit in row order (the minimum-id parent).  The
+//   wave's ballot of found lanes is the next-frontier word and updates the
+//   visited word, so the sweep needs no atomics except three counters per
+//   workgroup.
+#include "bfs_internal.h"
+
+namespace bfsk {
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    return (1ull << lane_id()) - 1ull;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, WAVE);
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+    for (int d = 1; d < WAVE; d <<= 1) {
+        T y = __shfl_up(x, d, WAVE);
+        if (lane_id() >= d) x += y;
+    }
+    return x;
+}
+
+// Sum of (a, b, c) over the workgroup, added once to three counters.
+template <int NWAVES>
+__device__ __forceinline__ void block_add3(uint64_t a, uint64_t b, uint64_t c, uint64_t* ca, uint64_t* cb,
+                                           uint64_t* cc) {
+    __shared__ uint64_t red[3][NWAVES];
+    a = wave_sum(a); b = wave_sum(b); c = wave_sum(c);
+    int wid = threadIdx.x / WAVE;
+    if (lane_id() == 0) { red[0][wid] = a; red[1][wid] = b; red[2][wid] = c; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t x = 0, y = 0, z = 0;
+        for (int i = 0; i < NWAVES; ++i) { x += red[0][i]; y += red[1][i]; z += red[2][i]; }
+        if (x && ca) atomicAdd((unsigned long long*)ca, (unsigned long long)x);
+        if (y && cb) atomicAdd((unsigned long long*)cb, (unsigned long long)y);
+        if (z && cc) atomicAdd((unsigned long long*)cc, (unsigned long long)z);
+    }
+}
+
+static inline int grid_for(int64_t items, int per_block, int cap) {
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+// ------------------------------------------------------------------ init
+__global__ void k_init(int32_t* __restrict__ parent, int32_t* __restrict__ depth, int64_t n,
+                       uint64_t* __restrict__ visited, uint64_t* __restrict__ fbits, uint64_t* __restrict__ claim,
+                       int64_t W, int32_t* __restrict__ queue, int64_t src, uint64_t* __restrict__ counters) {
+    int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = tid; v < n; v += stride) {
+        bool s = v == src;
+        parent[v] = s ? (int32_t)src : -1;
+        depth[v] = s ? 0 : -1;
+    }
+    for (int64_t w = tid; w < W; w += stride) {
+        // ids >= n in the last word count as visited so its wave can finish
+        uint64_t pad = (w == W - 1 && (n & 63)) ? (~0ull << (n & 63)) : 0ull;
+        uint64_t sb = (w == (src >> 6)) ? (1ull << (src & 63)) : 0ull;
+        visited[w] = pad | sb;
+        fbits[w] = sb;
+        claim[w] = 0;
+    }
+    if (tid == 0) queue[0] = (int32_t)src;
+    if (tid < SLOTS * SLOT_WORDS) counters[tid] = 0;
+}
+
+void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, uint64_t* visited, uint64_t* fbits,
+                 uint64_t* claim, int64_t W, int32_t* queue, int64_t src, uint64_t* counters) {
+    int g = grid_for(n > W ? n : W, 256, L.grid_cap * 4);
+    hipLaunchKernelGGL(k_init, dim3(g), dim3(256), 0, L.stream, parent, depth, n, visited, fbits, claim, W, queue,
+                       src, counters);
+}
+
+// ------------------------------------------------------------------ frontier degree scan
+template <typename OffT>
+__device__ __forceinline__ int64_t qdeg(const OffT* off, const int32_t* q, int64_t i) {
+    int32_t u = q[i];
+    return (int64_t)off[u + 1] - (int64_t)off[u];
+}
+
+// per-workgroup sums of SCAN_TILE queue entries' degrees
+template <typename OffT>
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_partials(const OffT* __restrict__ off,
+                                                               const int32_t* __restrict__ q, int64_t qlen,
+                                                               int64_t* __restrict__ partial) {
+    __shared__ int64_t red[SCAN_BLOCK / WAVE];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    int64_t s = 0;
+    for (int k = 0; k < SCAN_IPT; ++k)
+        if (base + k < qlen) s += qdeg(off, q, base + k);
+    s = wave_sum(s);
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int i = 0; i < SCAN_BLOCK / WAVE; ++i) t += red[i];
+        partial[blockIdx.x] = t;
+    }
+}
+
+// exclusive scan of partial[0..nb) in place, one workgroup
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_top(int64_t* __restrict__ partial, int64_t nb) {
+    __shared__ int64_t wsum[SCAN_BLOCK / WAVE];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nb; c0 += SCAN_BLOCK) {
+        int64_t i = c0 + threadIdx.x;
+        int64_t x = i < nb ? partial[i] : 0;
+        int64_t inc = wave_incl_scan(x);
+        int wid = threadIdx.x / WAVE;
+        if (lane_id() == WAVE - 1) wsum[wid] = inc;
+        __syncthreads();
+        if (wid == 0) {
+            int64_t t = lane_id() < SCAN_BLOCK / WAVE ? wsum[lane_id()] : 0;
+            t = wave_incl_scan(t);
+            if (lane_id() < SCAN_BLOCK / WAVE) wsum[lane_id()] = t;
+        }
+        __syncthreads();
+        int64_t before = (wid ? wsum[wid - 1] : 0) + carry;
+        if (i < nb) partial[i] = before + inc - x;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += wsum[SCAN_BLOCK / WAVE - 1];
+        __syncthreads();
+    }
+}
+
+// scan[i] for every queue entry, scan[qlen] = total, and the tile partition:
+// the entry whose edge range [scan[i], scan[i]+deg) holds t*TD_TILE owns tile t.
+template <typename OffT>
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const OffT* __restrict__ off,
+                                                            const int32_t* __restrict__ q, int64_t qlen,
+                                                            const int64_t* __restrict__ partial, int64_t total,
+                                                            int64_t ntiles, int64_t* __restrict__ scan,
+                                                            int32_t* __restrict__ tile_start) {
+    __shared__ int64_t wsum[SCAN_BLOCK / WAVE];
+    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    int64_t d[SCAN_IPT];
+    int64_t s = 0;
+    for (int k = 0; k < SCAN_IPT; ++k) {
+        d[k] = (base + k < qlen) ? qdeg(off, q, base + k) : 0;
+        s += d[k];
+    }
+    int64_t inc = wave_incl_scan(s);
+    int wid = threadIdx.x / WAVE;
+    if (lane_id() == WAVE - 1) wsum[wid] = inc;
+    __syncthreads();
+    if (wid == 0) {
+        int64_t t = lane_id() < SCAN_BLOCK / WAVE ? wsum[lane_id()] : 0;
+        t = wave_incl_scan(t);
+        if (lane_id() < SCAN_BLOCK / WAVE) wsum[lane_id()] = t;
+    }
+    __syncthreads();
+    int64_t run = (partial ? partial[blockIdx.x] : 0) + (wid ? wsum[wid - 1] : 0) + inc - s;
+    for (int k = 0; k < SCAN_IPT; ++k) {
+        int64_t i = base + k;
+        if (i >= qlen) break;
+        scan[i] = run;
+        if (d[k] > 0) {
+            int64_t t0 = (run + TD_TILE - 1) / TD_TILE;
+            int64_t t1 = (run + d[k] - 1) / TD_TILE;
+            for (int64_t t = t0; t <= t1; ++t) tile_start[t] = (int32_t)i;
+        }
+        run += d[k];
+    }
+    if (base <= qlen - 1 && qlen - 1 < base + SCAN_IPT) {
+        scan[qlen] = total;
+        tile_start[ntiles] = (int32_t)(qlen - 1);
+    }
+}
+
+template <typename OffT>
+int launch_td_scan(const Launch& L, const OffT* off, const int32_t* q, int64_t qlen, int64_t total, int64_t* scan,
+                   int32_t* tile_start, int64_t* partial) {
+    int64_t nb = (qlen + SCAN_TILE - 1) / SCAN_TILE;
+    int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
+    int launches = 1;
+    if (nb > 1) {
+        hipLaunchKernelGGL(k_scan_partials<OffT>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, L.stream, off, q, qlen,
+                           partial);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, L.stream, partial, nb);
+        launches += 2;
+    }
+    hipLaunchKernelGGL(k_scan_apply<OffT>, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(SCAN_BLOCK), 0, L.stream, off,
+                       q, qlen, nb > 1 ? (const int64_t*)partial : nullptr, total, ntiles, scan, tile_start);
+    return launches;
+}
+
+// ------------------------------------------------------------------ top-down expand
+template <typename OffT, bool MIN>
+__global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
+    const OffT* __restrict__ off, const int32_t* __restrict__ cols, const int32_t* __restrict__ q,
+    const int64_t* __restrict__ scan, const int32_t* __restrict__ tile_start, int64_t qlen, int64_t total,
+    int64_t ntiles, int64_t nnz, int32_t* __restrict__ parent, int32_t* __restrict__ depth, uint64_t* __restrict__ visited,
+    uint64_t* __restrict__ claim, int32_t* __restrict__ qnext, uint64_t* __restrict__ slot,
+    uint64_t* __restrict__ zslot, int32_t next_depth) {
+    __shared__ int32_t s_start[TD_TILE + 1];   // first edge of staged vertex j, relative to the tile
+    __shared__ int64_t s_base[TD_TILE + 1];    // off[u_j] - scan[j]: cols index = s_base[j] + edge index
+    __shared__ int32_t s_u[TD_TILE + 1];
+    __shared__ int32_t s_out[TD_TILE];
+    __shared__ int s_cnt;
+    __shared__ uint64_t s_qbase;
+
+    if (blockIdx.x == 0 && threadIdx.x < SLOT_WORDS && zslot) zslot[threadIdx.x] = 0;
+    uint64_t my_n = 0, my_m = 0;
+    const int lane = lane_id();
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t e0 = t * TD_TILE;
+        const int64_t e1 = (e0 + TD_TILE < total) ? e0 + TD_TILE : total;
+        const int i0 = tile_start[t];
+        int nv = tile_start[t + 1] - i0 + 1;
+        // every queued vertex has an out-edge, so a tile spans at most
+        // TD_TILE + 1 of them; the clamps only guard memory
+        if (nv > TD_TILE + 1) nv = TD_TILE + 1;
+        if (i0 < 0 || i0 >= qlen) nv = 0;
+        else if (nv > qlen - i0) nv = (int)(qlen - i0);
+        for (int j = threadIdx.x; j < nv; j += TD_BLOCK) {
+            int32_t u = q[i0 + j];
+            int64_t sc = scan[i0 + j];
+            int64_t rel = sc - e0;
+            s_start[j] = rel < 0 ? 0 : (int32_t)rel;
+            s_base[j] = (int64_t)off[u] - sc;
+            s_u[j] = u;
+        }
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        for (int k = 0; k < TD_EPT; ++k) {
+            const int p = k * TD_BLOCK + threadIdx.x;
+            const int64_t e = e0 + p;
+            bool won = false;
+            int32_t v = 0;
+            int64_t dv = 0;
+            if (e < e1 && nv > 0) {
+                int lo = 0, hi = nv - 1;   // last staged vertex starting at or before p
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (s_start[mid] <= p) lo = mid; else hi = mid - 1;
+                }
+                const int32_t u = s_u[lo];
+                int64_t pos = s_base[lo] + e;
+                if (pos < 0 || pos >= nnz) pos = 0;   // unreachable for a consistent scan
+                v = cols[pos];
+                const uint64_t bit = 1ull << (v & 63);
+                if (!(visited[v >> 6] & bit)) {
+                    if (MIN) {
+                        atomicMin((unsigned int*)&parent[v], (unsigned int)u);
+                        uint64_t old = atomicOr((unsigned long long*)&claim[v >> 6], (unsigned long long)bit);
+                        won = !(old & bit);
+                    } else {
+                        won = atomicCAS(&parent[v], -1, u) == -1;
+                        if (won) atomicOr((unsigned long long*)&visited[v >> 6], (unsigned long long)bit);
+                    }
+                }
+                if (won) {
+                    depth[v] = next_depth;
+                    dv = (int64_t)off[v + 1] - (int64_t)off[v];
+                    my_n += 1;
+                    my_m += (uint64_t)dv;
+                }
+            }
+            // vertices without out-edges are discovered but never expanded
+            const bool push = won && dv > 0;
+            const uint64_t wm = __ballot(push);
+            if (wm) {
+                const int leader = __ffsll((unsigned long long)wm) - 1;
+                int b = 0;
+                if (lane == leader) b = atomicAdd(&s_cnt, __popcll(wm));
+                b = __shfl(b, leader, WAVE);
+                if (push) s_out[b + __popcll(wm & lanemask_lt())] = v;
+            }
+        }
+        __syncthreads();
+        const int cnt = s_cnt;
+        if (threadIdx.x == 0 && cnt > 0)
+            s_qbase = atomicAdd((unsigned long long*)&slot[S_QLEN], (unsigned long long)cnt);
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt; j += TD_BLOCK) qnext[s_qbase + j] = s_out[j];
+        __syncthreads();
+    }
+    block_add3<TD_BLOCK / WAVE>(my_n, my_m, 0, &slot[S_NNEXT], &slot[S_MNEXT], nullptr);
+}
+
+template <typename OffT>
+void launch_td_expand(const Launch& L, bool min_mode, const OffT* off, const int32_t* cols, int64_t nnz,
+                      const int32_t* q, int64_t qlen, const int64_t* scan, const int32_t* tile_start, int64_t total,
+                      int32_t* parent, int32_t* depth, uint64_t* visited, uint64_t* claim, int32_t* qnext,
+                      uint64_t* slot, uint64_t* zslot, int32_t next_depth) {
+    int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
+    int g = grid_for(ntiles, 1, L.grid_cap);
+    if (min_mode)
+        hipLaunchKernelGGL((k_td_expand<OffT, true>), dim3(g), dim3(TD_BLOCK), 0, L.stream, off, cols, q, scan,
+                           tile_start, qlen, total, ntiles, nnz, parent, depth, visited, claim, qnext, slot,
+                           zslot, next_depth);
+    else
+        hipLaunchKernelGGL((k_td_expand<OffT, false>), dim3(g), dim3(TD_BLOCK), 0, L.stream, off, cols, q, scan,
+                           tile_start, qlen, total, ntiles, nnz, parent, depth, visited, claim, qnext, slot,
+                           zslot, next_depth);
+}
+
+// ------------------------------------------------------------------ bottom-up sweep
+template <typename OffT>
+__global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
+    const OffT* __restrict__ off, const int32_t* __restrict__ cols, const uint64_t* __restrict__ fbits,
+    uint64_t* __restrict__ nbits, uint64_t* __restrict__ visited, int32_t* __restrict__ parent,
+    int32_t* __restrict__ depth, int64_t n, int64_t W, int32_t next_depth, int serial_len,
+    uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot) {
+    if (blockIdx.x == 0 && threadIdx.x < SLOT_WORDS && zslot) zslot[threadIdx.x] = 0;
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (BU_BLOCK / WAVE);
+    uint64_t my_n = 0, my_m = 0, my_x = 0;
+    for (int64_t w = (int64_t)blockIdx.x * (BU_BLOCK / WAVE) + threadIdx.x / WAVE; w < W; w += nwaves) {
+        const uint64_t vis = visited[w];
+        if (vis == ~0ull) {
+            if (lane == 0) nbits[w] = 0;
+            continue;
+        }
+        const int64_t v = w * WAVE + lane;
+        const bool active = !((vis >> lane) & 1ull);
+        int64_t beg = 0, end = 0;
+        if (active) {
+            beg = (int64_t)off[v];
+            end = (int64_t)off[v + 1];
+        }
+        int64_t p = beg;
+        const int64_t lim = (end - beg > serial_len) ? beg + serial_len : end;
+        int32_t par = -1;
+        while (p < lim) {
+            const int32_t c = cols[p];
+            if ((fbits[c >> 6] >> (c & 63)) & 1ull) { par = c; break; }
+            ++p;
+        }
+        // rows still open after the serial part: the whole wave scans them,
+        // one at a time, 64 entries per step, first hit in row order
+        uint64_t rem = __ballot(active && par < 0 && p < end);
+        while (rem) {
+            const int l = __ffsll((unsigned long long)rem) - 1;
+            rem &= rem - 1;
+            const int64_t pb = __shfl(p, l, WAVE);
+            const int64_t pe = __shfl(end, l, WAVE);
+            int32_t got = -1;
+            int64_t gotpos = pe;
+            for (int64_t b = pb; b < pe; b += WAVE) {
+                const int64_t idx = b + lane;
+                bool hit = false;
+                int32_t c = 0;
+                if (idx < pe) {
+                    c = cols[idx];
+                    hit = (fbits[c >> 6] >> (c & 63)) & 1ull;
+                }
+                const uint64_t hm = __ballot(hit);
+                if (hm) {
+                    const int f = __ffsll((unsigned long long)hm) - 1;
+                    got = __shfl(c, f, WAVE);
+                    gotpos = b + f;
+                    break;
+                }
+            }
+            if (lane == l) { par = got; p = gotpos; }
+        }
+        const bool found = par >= 0;
+        const uint64_t fm = __ballot(found);
+        if (lane == 0) {
+            nbits[w] = fm;
+            if (fm) visited[w] = vis | fm;
+        }
+        if (found) {
+            parent[v] = par;
+            depth[v] = next_depth;
+            my_n += 1;
+            my_m += (uint64_t)(end - beg);
+            my_x += (uint64_t)(p - beg + 1);
+        } else if (active) {
+            my_x += (uint64_t)(end - beg);
+        }
+    }
+    block_add3<BU_BLOCK / WAVE>(my_n, my_m, my_x, &slot[S_NNEXT], &slot[S_MNEXT], &slot[S_EXAMINED]);
+}
+
+template <typename OffT>
+void launch_bu_sweep(const Launch& L, const OffT* off, const int32_t* cols, const uint64_t* fbits, uint64_t* nbits,
+                     uint64_t* visited, int32_t* parent, int32_t* depth, int64_t n, int64_t W, int32_t next_depth,
+                     int serial_len, uint64_t* slot, uint64_t* zslot) {
+    int g = grid_for(W, BU_BLOCK / WAVE, L.grid_cap);
+    hipLaunchKernelGGL(k_bu_sweep<OffT>, dim3(g), dim3(BU_BLOCK), 0, L.stream, off, cols, fbits, nbits, visited,
+                       parent, depth, n, W, next_depth, serial_len, slot, zslot);
+}
+
+// ------------------------------------------------------------------ conversions
+__global__ void k_clear_words(uint64_t* __restrict__ w, int64_t nw) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride) w[i] = 0;
+}
+
+void launch_clear_words(const Launch& L, uint64_t* w, int64_t nw) {
+    hipLaunchKernelGGL(k_clear_words, dim3(grid_for(nw, 256, L.grid_cap * 4)), dim3(256), 0, L.stream, w, nw);
+}
+
+__global__ void k_queue_to_bitmap(const int32_t* __restrict__ q, int64_t qlen, uint64_t* __restrict__ bits) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < qlen; i += stride) {
+        int32_t v = q[i];
+        atomicOr((unsigned long long*)&bits[v >> 6], 1ull << (v & 63));
+    }
+}
+
+void launch_queue_to_bitmap(const Launch& L, const int32_t* q, int64_t qlen, uint64_t* bits) {
+    hipLaunchKernelGGL(k_queue_to_bitmap, dim3(grid_for(qlen, 256, L.grid_cap * 4)), dim3(256), 0, L.stream, q,
+                       qlen, bits);
+}
+
+// one word per thread; workgroup-wide exclusive scan of popcounts gives each
+// thread its output position, one global atomicAdd per workgroup iteration
+__global__ __launch_bounds__(256) void k_bitmap_to_queue(const uint64_t* __restrict__ bits, int64_t W,
+                                                         int32_t* __restrict__ q, uint64_t* __restrict__ qlen_ctr) {
+    __shared__ int wsum[256 / WAVE];
+    __shared__ uint64_t s_base;
+    for (int64_t w0 = (int64_t)blockIdx.x * 256; w0 < W; w0 += (int64_t)gridDim.x * 256) {
+        const int64_t w = w0 + threadIdx.x;
+        uint64_t x = (w < W) ? bits[w] : 0ull;
+        int c = __popcll(x);
+        int inc = wave_incl_scan(c);
+        int wid = threadIdx.x / WAVE;
+        if (lane_id() == WAVE - 1) wsum[wid] = inc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int i = 0; i < 256 / WAVE; ++i) { int t = wsum[i]; wsum[i] = tot; tot += t; }
+            s_base = tot ? atomicAdd((unsigned long long*)qlen_ctr, (unsigned long long)tot) : 0;
+        }
+        __syncthreads();
+        int64_t pos = (int64_t)s_base + wsum[wid] + inc - c;
+        while (x) {
+            int b = __ffsll((unsigned long long)x) - 1;
+            x &= x - 1;
+            q[pos++] = (int32_t)(w * 64 + b);
+        }
+        __syncthreads();
+    }
+}
+
+void launch_bitmap_to_queue(const Launch& L, const uint64_t* bits, int64_t W, int32_t* q, uint64_t* qlen_ctr) {
+    hipLaunchKernelGGL(k_bitmap_to_queue, dim3(grid_for(W, 256, L.grid_cap)), dim3(256), 0, L.stream, bits, W, q,
+                       qlen_ctr);
+}
+
+__global__ void k_merge_claim(uint64_t* __restrict__ visited, uint64_t* __restrict__ claim, int64_t W) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < W; i += stride) {
+        uint64_t c = claim[i];
+        if (c) {
+            visited[i] |= c;
+            claim[i] = 0;
+        }
+    }
+}
+
+void launch_merge_claim(const Launch& L, uint64_t* visited, uint64_t* claim, int64_t W) {
+    hipLaunchKernelGGL(k_merge_claim, dim3(grid_for(W, 256, L.grid_cap * 4)), dim3(256), 0, L.stream, visited,
+                       claim, W);
+}
+
+// ------------------------------------------------------------------ validation
+// one wave per row: offsets monotone, ids in range, rows ascending (SORTED),
+// and for SYMMETRIC|SORTED every (u,v) has (v,u), found by binary search.
+template <typename OffT>
+__global__ __launch_bounds__(256) void k_validate_csr(const OffT* __restrict__ off, const int32_t* __restrict__ cols,
+                                                      int64_t n, int64_t nnz, uint32_t flags,
+                                                      uint32_t* __restrict__ err) {
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (256 / WAVE);
+    uint32_t e = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if ((int64_t)off[0] != 0 || (int64_t)off[n] != nnz) e |= VE_OFFSETS;
+    }
+    for (int64_t u = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE; u < n; u += nwaves) {
+        const int64_t b = (int64_t)off[u], en = (int64_t)off[u + 1];
+        if (en < b || b < 0 || en > nnz) { e |= VE_OFFSETS; continue; }
+        for (int64_t p = b + lane; p < en; p += WAVE) {
+            const int32_t c = cols[p];
+            if (c < 0 || (int64_t)c >= n) { e |= VE_RANGE; continue; }
+            if ((flags & 2u) && p + 1 < en && cols[p + 1] < c) e |= VE_UNSORTED;
+            if ((flags & 3u) == 3u) {
+                int64_t lo = (int64_t)off[c], hi = (int64_t)off[c + 1];
+                if (lo < 0 || hi > nnz || hi < lo) { e |= VE_OFFSETS; continue; }
+                bool ok = false;
+                while (lo < hi) {
+                    int64_t mid = (lo + hi) >> 1;
+                    int32_t x = cols[mid];
+                    if (x == (int32_t)u) { ok = true; break; }
+                    if (x < (int32_t)u) lo = mid + 1; else hi = mid;
+                }
+                if (!ok) e |= VE_ASYM;
+            }
+        }
+    }
+    if (e) atomicOr(err, e);
+}
+
+template <typename OffT>
+void launch_validate_csr(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, int64_t nnz,
+                         uint32_t flags, uint32_t* err) {
+    int g = grid_for(n, 256 / WAVE, L.grid_cap);
+    hipLaunchKernelGGL(k_validate_csr<OffT>, dim3(g), dim3(256), 0, L.stream, off, cols, n, nnz, flags, err);
+}
+
+// ------------------------------------------------------------------ instantiations
+#define BFS_INST(T)                                                                                              \
+    template int launch_td_scan<T>(const Launch&, const T*, const int32_t*, int64_t, int64_t, int64_t*,        \
+                                   int32_t*, int64_t*);                                                         \
+    template void launch_td_expand<T>(const Launch&, bool, const T*, const int32_t*, int64_t, const int32_t*, \
+                                      int64_t, const int64_t*, const int32_t*, int64_t, int32_t*, int32_t*,     \
+                                      uint64_t*, uint64_t*, int32_t*, uint64_t*, uint64_t*, int32_t);            \
+    template void launch_bu_sweep<T>(const Launch&, const T*, const int32_t*, const uint64_t*, uint64_t*,      \
+                                     uint64_t*, int32_t*, int32_t*, int64_t, int64_t, int32_t, int, uint64_t*,  \
+                                     uint64_t*);                                                                \
+    template void launch_validate_csr<T>(const Launch&, const T*, const int32_t*, int64_t, int64_t, uint32_t,  \
+                                         uint32_t*);
+BFS_INST(int32_t)
+BFS_INST(int64_t)
+
+}  // namespace bfsk
