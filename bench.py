@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark: single-source direction-optimizing BFS on one MI355X.
+
+Workload (default): Kronecker graph, scale 26, edgefactor 16, initiator
+(.57,.19,.19,.05), vertex ids permuted, cleaned and symmetrised, int64
+offsets + int32 columns resident in HBM; 64 seeded sources of nonzero degree;
+alpha = 15, beta = 18.  One step = one search from one source (the sources are
+cycled).  value = harmonic-mean GTEPS = m * K / (wall time of the K timed
+steps), m = undirected edges after cleanup (nnz / 2), the TEPS convention of
+the paper's experimental-design section.
+
+Also reported:
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                average HIP-event duration (events recorded by the library on
+                the launch stream during the timed steps), against 8 TB/s;
+                `traffic` comes from the committed rocprofv3 FETCH_SIZE /
+                WRITE_SIZE summary when it was taken on the current kernel source.
+  cpu_baseline  the CPU oracle (serial Alg. 1) timed on this host on a bounded
+                sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "harmonic-mean GTEPS @ Kronecker scale 26; batched queries/s + p99 latency"
+PROFILE_PMC = os.path.join(ROOT, "profiles", "bu_sweep_kron26_pmc.md")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha1()
+    csrc = os.path.join(ROOT, "paper_1705_04590_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def level_bytes(st: dict, n: int, wo: int):
+    """Algorithmic HBM bytes of every expansion launch, per level.
+
+    top-down level : |F|(4 + 2 W_o) + D_F (4 column + 4 probe) + |N| (4 parent + 4 depth + 4 queue)
+    bottom-up level: n/8 visited + 2 W_o |U| + 4 X + n/8 frontier + 8 |N| + n/8 next/visited
+    with F the frontier, D_F its edges, N the next frontier, U the unvisited
+    vertices that have edges (vertices without edges are never scanned) and
+    X the adjacency entries examined up to the first hit.
+    """
+    L = len(st["level_dir"])
+    out = []
+    for d in range(L):
+        nf, mf = st["level_nf"][d], st["level_mf"][d]
+        nn = st["level_nf"][d + 1] if d + 1 < L else 0
+        if st["level_dir"][d] == 0:
+            b = nf * (4 + 2 * wo) + mf * 8 + nn * 12 if mf > 0 else 0
+            out.append(("td_expand", b))
+        else:
+            u, x = max(st["level_unvisited"][d] - st["isolated"], 0), st["level_examined"][d]
+            b = 3 * (n / 8) + 2 * wo * u + 4 * x + 8 * nn
+            out.append(("bu_sweep", b))
+    return out
+
+
+def read_traffic(kernel: str):
+    """Per-launch HBM bytes from the committed PMC summary, if it matches the current kernels."""
+    if not os.path.exists(PROFILE_PMC):
+        return None
+    txt = open(PROFILE_PMC).read()
+    m = re.search(r"```json\s*(\{.*?\})\s*```", txt, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("kernel") != kernel:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(off, cols, sources, m, max_seconds):
+    import oracle
+    orc = oracle.load()
+    t_total, done = 0.0, 0
+    for s in sources:
+        t0 = time.perf_counter()
+        orc.bfs(off, cols, int(s))
+        t_total += time.perf_counter() - t0
+        done += 1
+        if t_total >= max_seconds:
+            break
+    return {"value": m * done / t_total / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"{done} of the {len(sources)} sources, full graph, serial Alg. 1 oracle (one thread), "
+                      f"{t_total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=64)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=26)
+    ap.add_argument("--edgefactor", type=int, default=16)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--source-seed", type=int, default=2)
+    ap.add_argument("--nsources", type=int, default=64)
+    ap.add_argument("--dir", choices=["do", "td", "bu"], default="do")
+    ap.add_argument("--parent-mode", choices=["any", "min"], default="any")
+    ap.add_argument("--alpha", type=float, default=15.0)
+    ap.add_argument("--beta", type=float, default=18.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run three 1 GiB device-to-device copies (the plain copy kernel "
+                         "that scales FETCH_SIZE / WRITE_SIZE counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is described "
+              "in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1705_04590_amd as bfs
+
+    t0 = time.time()
+    log(f"[bench] generating Kronecker scale {args.scale} edgefactor {args.edgefactor} seed {args.seed}")
+    off, cols = graphgen.kronecker(args.scale, args.edgefactor, seed=args.seed)
+    n = off.size - 1
+    nnz = int(off[-1])
+    m = nnz // 2
+    log(f"[bench] n={n} nnz={nnz} m={m} generated in {time.time() - t0:.1f}s")
+    sources = graphgen.random_sources(off, args.nsources, seed=args.source_seed)
+
+    dev = torch.device("cuda:0")
+    use32 = nnz < 2 ** 31 and args.scale < 22
+    d_off = torch.from_numpy(off.astype(np.int32) if use32 else off).to(dev)
+    d_cols = torch.from_numpy(cols).to(dev)
+    g = bfs.bfs_create_graph_csr(d_off, d_cols, bfs.BFS_GRAPH_SYMMETRIC | bfs.BFS_GRAPH_SORTED)
+    ws = bfs.workspace(g, 1, dev)
+    parent = torch.empty(n, dtype=torch.int32, device=dev)
+    depth = torch.empty(n, dtype=torch.int32, device=dev)
+    opts = bfs.bfs_opts_default(dir={"do": 0, "td": 1, "bu": 2}[args.dir],
+                                parent_mode=1 if args.parent_mode == "min" else 0,
+                                alpha=args.alpha, beta=args.beta, timing=0 if args.no_timing else 1)
+    stream = torch.cuda.current_stream()
+    log(f"[bench] graph resident ({(d_off.numel() * d_off.element_size() + nnz * 4) / 2**30:.2f} GiB), "
+        f"workspace {ws.numel() / 2**30:.2f} GiB; warmup {args.warmup}")
+    for i in range(args.warmup):
+        bfs.bfs_run(g, int(sources[i % len(sources)]), parent, depth, ws, opts, stream)
+    torch.cuda.synchronize()
+
+    log(f"[bench] timing {args.steps} steps")
+    stats = []
+    torch.cuda.synchronize()
+    t_begin = time.perf_counter()
+    for i in range(args.steps):
+        st = bfs.bfs_run(g, int(sources[i % len(sources)]), parent, depth, ws, opts, stream)
+        stats.append(st.as_dict())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_begin
+    gteps = m * args.steps / elapsed / 1e9
+    per_source_ms = [s["total_ms"] for s in stats]
+    log(f"[bench] {args.steps} searches in {elapsed:.3f}s -> {gteps:.2f} GTEPS "
+        f"(per-search ms p50 {np.percentile(per_source_ms, 50):.2f} p99 {np.percentile(per_source_ms, 99):.2f})")
+
+    # ---- roofline of the dominant kernel (HIP events recorded on the launch stream)
+    roofline = None
+    kernel_totals = {}
+    if not args.no_timing:
+        for s in stats:
+            for k, v in s["kernel_ms"].items():
+                kernel_totals[k] = kernel_totals.get(k, 0.0) + v
+        dom = max(("td_expand", "bu_sweep"), key=lambda k: kernel_totals.get(k, 0.0))
+        wo = d_off.element_size()
+        nbytes, launches, ms = 0.0, 0, 0.0
+        for s in stats:
+            for d, (kind, b) in enumerate(level_bytes(s, n, wo)):
+                if kind == dom and (kind != "td_expand" or s["level_mf"][d] > 0):
+                    nbytes += b
+                    launches += 1
+                    ms += s["level_ms"][d]
+        if launches and ms > 0:
+            avg_s = ms / launches / 1e3
+            achieved = nbytes / launches / avg_s / 1e9
+            traffic = read_traffic(dom)
+            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                        "launches": launches, "avg_launch_us": round(avg_s * 1e6, 2),
+                        "alg_bytes_per_launch": round(nbytes / launches)}
+        log(f"[bench] kernel ms over timed steps: " +
+            ", ".join(f"{k}={v:.2f}" for k, v in sorted(kernel_totals.items(), key=lambda x: -x[1]) if v))
+
+    if args.copy_calibration:
+        src_t = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst_t = torch.empty_like(src_t)
+        for _ in range(3):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        del src_t, dst_t
+        log("[bench] copy calibration: 3 x 1 GiB device copies done")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle baseline (budget {args.cpu_seconds}s)")
+        cpu = cpu_baseline(off, cols, sources, m, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC, "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"kronecker_s{args.scale}_ef{args.edgefactor}_single_source_{args.dir}",
+                   "scale": args.scale, "edgefactor": args.edgefactor, "n": n, "nnz": nnz, "m_undirected": m,
+                   "sources": len(sources), "offsets": "int32" if use32 else "int64",
+                   "parent_mode": args.parent_mode, "alpha": args.alpha, "beta": args.beta,
+                   "levels_p50": int(np.median([s["levels"] for s in stats])),
+                   "search_ms_p50": round(float(np.percentile(per_source_ms, 50)), 3),
+                   "search_ms_p99": round(float(np.percentile(per_source_ms, 99)), 3),
+                   "kernel_ms_total": {k: round(v, 3) for k, v in kernel_totals.items() if v}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    g.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -17,9 +17,10 @@
  *   - Ownership: every device buffer (graph arrays, outputs, workspace) is
  *     allocated and freed by the caller.  A graph handle borrows the graph
  *     arrays until bfs_destroy_graph; the library never frees caller
- *     memory.  The library allocates only small metadata at create time
- *     (a pinned host counter buffer, HIP events, and for DCSC graphs
- *     nothing on the device).
+ *     memory.  The library allocates only metadata at create time: a
+ *     pinned host counter buffer, HIP events, and for symmetric CSR
+ *     graphs one n/8-byte device bitmap of the vertices without entries
+ *     (freed by bfs_destroy_graph).
  *   - Asynchrony: kernels run on the HIP stream passed in (NULL = the null
  *     stream).  bfs_run / bfs_run_multi drive the level loop from the host
  *     and synchronise that stream once per level to read three counters, so
@@ -60,8 +61,11 @@ typedef enum {
 typedef enum { BFS_DIR_DO = 0, BFS_DIR_TD = 1, BFS_DIR_BU = 2 } bfs_dir;
 
 /* Which parent is reported.  Section 2: any vertex one level closer to the
- * source with an edge to v is a valid parent.  ANY claims v with an atomic
- * compare-and-swap (first claimer wins).  MIN reports the smallest such id:
+ * source with an edge to v is a valid parent.  ANY: in top-down levels the
+ * first thread to claim v wins -- an atomic fetch-or on v's bit of a claim
+ * bitmap (default) or a compare-and-swap on parent[v] (bfs_opts.td_claim);
+ * in bottom-up levels v takes the first frontier entry of its row.  MIN
+ * reports the smallest such id:
  * the (select2nd, min) semiring of Section 4.2 in top-down levels and the
  * first hit over a sorted row in bottom-up levels.  MIN needs sorted rows
  * when a bottom-up level can run.                                          */
@@ -95,7 +99,9 @@ typedef struct {
     int32_t timing;        /* nonzero: HIP events around every kernel -> stats     */
     int32_t bu_serial;     /* entries a lane scans alone before its wave helps (0 = default) */
     int32_t grid_blocks;   /* cap on workgroups of grid-stride kernels (0 = default) */
-    int32_t reserved[9];
+    int32_t td_claim;      /* ANY parents, top-down claim: 0 = atomic fetch-or on a
+                              claim bitmap, 1 = compare-and-swap on parent[]     */
+    int32_t reserved[8];
 } bfs_opts;
 
 typedef struct {
@@ -103,6 +109,9 @@ typedef struct {
     int32_t td_levels, bu_levels;
     int32_t pad0;
     int64_t reached;                /* vertices with depth >= 0                      */
+    int64_t isolated;               /* symmetric graphs: vertices without entries
+                                       (never scanned: they start out visited);
+                                       0 for graphs not marked SYMMETRIC           */
     int64_t edges_examined;         /* adjacency entries examined (top-down: all
                                        entries of the frontier; bottom-up: entries
                                        up to and including the first hit)          */

@@ -150,17 +150,12 @@ int oracle_min_parent(int64_t n, const int64_t* off, const int32_t* cols, const 
 #define V_LEAK 7          /* edge u->v, u reached, v not reached          */
 #define V_SKIP 8          /* edge u->v, u reached, depth[v] > depth[u]+1  */
 
-static int row_contains(const int64_t* off, const int32_t* cols, int64_t u, int32_t v) {
-    for (int64_t p = off[u]; p < off[u + 1]; ++p)
-        if (cols[p] == v) return 1;
-    return 0;
-}
-
 /* Checks the BFS-tree invariants; *bad_vertex receives the first vertex
  * that violates one.  Together the invariants force depth to equal the
  * hop distance from s: edges from reached vertices never skip a level, so
  * depth <= distance along any shortest path; parent chains are real paths
- * of length depth, so distance <= depth.                                 */
+ * of length depth, so distance <= depth.  One pass over the edges marks
+ * every v whose claimed parent edge (parent[v], v) exists.               */
 int oracle_validate(int64_t n, const int64_t* off, const int32_t* cols, int64_t s,
                     const int32_t* parent, const int32_t* depth, int64_t* bad_vertex) {
     *bad_vertex = -1;
@@ -175,19 +170,24 @@ int oracle_validate(int64_t n, const int64_t* off, const int32_t* cols, int64_t 
     }
     for (int64_t v = 0; v < n; ++v) {
         if (depth[v] <= 0) continue;
-        int32_t u = parent[v];
-        if (!row_contains(off, cols, u, (int32_t)v)) { *bad_vertex = v; return V_NOT_EDGE; }
-        if (depth[u] != depth[v] - 1) { *bad_vertex = v; return V_PARENT_LEVEL; }
+        if (depth[parent[v]] != depth[v] - 1) { *bad_vertex = v; return V_PARENT_LEVEL; }
     }
-    for (int64_t u = 0; u < n; ++u) {
+    unsigned char* edge_ok = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!edge_ok) return -OR_E_NOMEM;
+    int code = 0;
+    for (int64_t u = 0; u < n && !code; ++u) {
         if (depth[u] < 0) continue;
         for (int64_t p = off[u]; p < off[u + 1]; ++p) {
             int32_t v = cols[p];
-            if (depth[v] < 0) { *bad_vertex = v; return V_LEAK; }
-            if (depth[v] > depth[u] + 1) { *bad_vertex = v; return V_SKIP; }
+            if (depth[v] < 0) { *bad_vertex = v; code = V_LEAK; break; }
+            if (depth[v] > depth[u] + 1) { *bad_vertex = v; code = V_SKIP; break; }
+            if (parent[v] == (int32_t)u) edge_ok[v] = 1;
         }
     }
-    return 0;
+    for (int64_t v = 0; v < n && !code; ++v)
+        if (depth[v] > 0 && !edge_ok[v]) { *bad_vertex = v; code = V_NOT_EDGE; }
+    free(edge_ok);
+    return code;
 }
 
 /* Per level d of a finished search (depth array):

@@ -43,12 +43,13 @@ class BfsError(RuntimeError):
 class bfs_opts(ctypes.Structure):
     _fields_ = [("dir", ctypes.c_int32), ("parent_mode", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("timing", ctypes.c_int32), ("bu_serial", ctypes.c_int32),
-                ("grid_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+                ("grid_blocks", ctypes.c_int32), ("td_claim", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
 
 
 class bfs_stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("td_levels", ctypes.c_int32), ("bu_levels", ctypes.c_int32),
-                ("pad0", ctypes.c_int32), ("reached", ctypes.c_int64), ("edges_examined", ctypes.c_int64),
+                ("pad0", ctypes.c_int32), ("reached", ctypes.c_int64), ("isolated", ctypes.c_int64),
+                ("edges_examined", ctypes.c_int64),
                 ("total_ms", ctypes.c_double), ("launches", ctypes.c_int64 * 8), ("kernel_ms", ctypes.c_double * 8),
                 ("level_dir", ctypes.c_int8 * STATS_MAX_LEVELS), ("level_nf", ctypes.c_int64 * STATS_MAX_LEVELS),
                 ("level_mf", ctypes.c_int64 * STATS_MAX_LEVELS), ("level_mu", ctypes.c_int64 * STATS_MAX_LEVELS),
@@ -60,7 +61,7 @@ class bfs_stats(ctypes.Structure):
         L = min(self.levels, STATS_MAX_LEVELS)
         return {
             "levels": self.levels, "td_levels": self.td_levels, "bu_levels": self.bu_levels,
-            "reached": self.reached, "edges_examined": self.edges_examined, "total_ms": self.total_ms,
+            "reached": self.reached, "isolated": self.isolated, "edges_examined": self.edges_examined, "total_ms": self.total_ms,
             "launches": {k: self.launches[i] for i, k in enumerate(KERNEL_KINDS)},
             "kernel_ms": {k: self.kernel_ms[i] for i, k in enumerate(KERNEL_KINDS)},
             "level_dir": list(self.level_dir[:L]), "level_nf": list(self.level_nf[:L]),

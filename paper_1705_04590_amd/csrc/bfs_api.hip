@@ -61,6 +61,10 @@ struct bfs_graph {
     int64_t nrows = 0, ncols = 0, row_base = 0, col_base = 0, nzc = 0, nzr = 0;
     const int32_t *jc = nullptr, *ir = nullptr, *jr = nullptr, *ic = nullptr;
     const int64_t *cp = nullptr, *rp = nullptr;
+    // derived metadata (device, library-owned, symmetric graphs only): bitmap
+    // of vertices without entries, ids >= n in the last word set; their count
+    uint64_t* d_iso = nullptr;
+    int64_t isolated = 0;
     // host metadata
     uint64_t* h_buf = nullptr;              // pinned: counter readback
     std::vector<hipEvent_t> events;         // timing pool
@@ -70,7 +74,7 @@ namespace {
 
 // -------------------------------------------------------------- workspace layout
 struct SingleLayout {
-    size_t counters, visited, fbits, nbits, claim, q0, q1, scan, tiles, partial, total;
+    size_t counters, visited, vprev, fbits, nbits, claim, q0, q1, scan, tiles, partial, total;
 };
 
 SingleLayout single_layout(const bfs_graph* g) {
@@ -81,6 +85,7 @@ SingleLayout single_layout(const bfs_graph* g) {
     size_t o = 0;
     L.counters = o; o = align_up(o + sizeof(uint64_t) * SLOTS * SLOT_WORDS);
     L.visited = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
+    L.vprev = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
     L.fbits = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
     L.nbits = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
     L.claim = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
@@ -151,6 +156,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     const SingleLayout Lo = single_layout(g);
     uint64_t* counters = (uint64_t*)(ws + Lo.counters);
     uint64_t* visited = (uint64_t*)(ws + Lo.visited);
+    uint64_t* vprev = (uint64_t*)(ws + Lo.vprev);
     uint64_t* fbits = (uint64_t*)(ws + Lo.fbits);
     uint64_t* nbits = (uint64_t*)(ws + Lo.nbits);
     uint64_t* claim = (uint64_t*)(ws + Lo.claim);
@@ -159,7 +165,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     int64_t* scan = (int64_t*)(ws + Lo.scan);
     int32_t* tiles = (int32_t*)(ws + Lo.tiles);
     int64_t* partial = (int64_t*)(ws + Lo.partial);
-    const bool min_mode = o.parent_mode == BFS_PARENT_MIN;
+    const int claim_mode = o.parent_mode == BFS_PARENT_MIN ? CLAIM_MIN : (o.td_claim == 1 ? CLAIM_CAS : CLAIM_BITMAP);
     const int serial = o.bu_serial > 0 ? o.bu_serial : 16;
     Launch L{stream, o.grid_blocks > 0 ? o.grid_blocks : 2048};
     Timer T{g, stream, o.timing != 0, {}, 0};
@@ -173,16 +179,17 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     const int64_t deg_s = (int64_t)hoff[1] - (int64_t)hoff[0];
 
     HIP_TRY(T.begin());
-    launch_init(L, parent, depth, n, visited, fbits, claim, W, qcur, src, counters);
+    launch_init(L, parent, depth, n, visited, vprev, fbits, claim, g->d_iso, W, qcur, src, counters);
     HIP_TRY(hipGetLastError());
     HIP_TRY(T.end(BFS_K_INIT, -1));
     if (st) st->launches[BFS_K_INIT] += 1;
 
-    int64_t n_f = 1, m_f = deg_s, m_u = g->nnz - deg_s, qlen = deg_s > 0 ? 1 : 0;
+    int64_t n_f = 1, m_f = deg_s, m_u = g->nnz - deg_s;
+    int64_t qlen = deg_s > 0 ? 1 : 0;     // exact queue length when qlen_dev is NULL
+    const uint64_t* qlen_dev = nullptr;   // set when the queue came from a bitmap conversion
     int64_t unvisited = n - 1;
     int cur_dir = (o.dir == BFS_DIR_BU) ? 1 : 0;
-    bool fmt_queue = true;       // frontier held as queue (true) or bitmap fbits (false)
-    bool fbits_fresh = true;     // fbits holds exactly the frontier (init sets {src})
+    bool fmt_queue = true;   // frontier as queue (true) or only as bitmap (false); fbits always holds it
     int level = 0;
     int64_t reached = 1, examined = 0;
     for (;;) {
@@ -194,63 +201,48 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
 
         uint64_t* slot = counters + (size_t)(level % SLOTS) * SLOT_WORDS;
         uint64_t* zslot = counters + (size_t)((level + 1) % SLOTS) * SLOT_WORDS;
-        if (cur_dir == 1 && fmt_queue) {
-            if (!fbits_fresh) {
-                HIP_TRY(T.begin());
-                launch_clear_words(L, fbits, W);
-                launch_queue_to_bitmap(L, qcur, qlen, fbits);
-                HIP_TRY(hipGetLastError());
-                HIP_TRY(T.end(BFS_K_CONVERT, level));
-                if (st) st->launches[BFS_K_CONVERT] += 2;
-            }
-            fmt_queue = false;
-        } else if (cur_dir == 0 && !fmt_queue) {
-            // the bitmap -> queue conversion counts into this level's slot
+        if (cur_dir == 0 && !fmt_queue) {
+            // bottom-up -> top-down: the frontier bitmap becomes a queue; its
+            // length stays on the device (slot word 4, cleared with the slot)
             HIP_TRY(T.begin());
-            launch_bitmap_to_queue(L, fbits, W, qcur, slot + S_EXAMINED + 1);
+            launch_bitmap_to_queue(L, fbits, W, qcur, slot + 4);
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_CONVERT, level));
             if (st) st->launches[BFS_K_CONVERT] += 1;
-            HIP_TRY(hipMemcpyAsync(h, slot + S_EXAMINED + 1, sizeof(uint64_t), hipMemcpyDeviceToHost, stream));
-            HIP_TRY(hipStreamSynchronize(stream));
-            qlen = (int64_t)h[0];
+            qlen_dev = slot + 4;
+            qlen = n_f;
             fmt_queue = true;
         }
 
         const int32_t next_depth = level + 1;
         if (cur_dir == 0) {
-            if (m_f > 0 && qlen > 0) {
+            if (m_f > 0) {
                 HIP_TRY(T.begin());
-                int nl = launch_td_scan<OffT>(L, off, qcur, qlen, m_f, scan, tiles, partial);
+                int nl = launch_td_scan<OffT>(L, off, qcur, qlen_dev, qlen, m_f, scan, tiles, partial);
                 HIP_TRY(hipGetLastError());
                 HIP_TRY(T.end(BFS_K_TD_SCAN, level));
                 HIP_TRY(T.begin());
-                launch_td_expand<OffT>(L, min_mode, off, g->cols, g->nnz, qcur, qlen, scan, tiles, m_f, parent,
-                                       depth, visited, claim, qnext, slot, zslot, next_depth);
+                launch_td_expand<OffT>(L, claim_mode, off, g->cols, g->nnz, qcur, qlen_dev, qlen, scan, tiles, m_f,
+                                       parent, depth, visited, claim, qnext, slot, zslot, next_depth);
                 HIP_TRY(hipGetLastError());
                 HIP_TRY(T.end(BFS_K_TD_EXPAND, level));
-                if (min_mode) {
-                    HIP_TRY(T.begin());
-                    launch_merge_claim(L, visited, claim, W);
-                    HIP_TRY(hipGetLastError());
-                    HIP_TRY(T.end(BFS_K_CONVERT, level));
-                }
+                HIP_TRY(T.begin());
+                launch_merge(L, claim_mode == CLAIM_MIN, visited, vprev, claim, fbits, W);
+                HIP_TRY(hipGetLastError());
+                HIP_TRY(T.end(BFS_K_CONVERT, level));
                 if (st) {
                     st->launches[BFS_K_TD_SCAN] += nl;
                     st->launches[BFS_K_TD_EXPAND] += 1;
-                    if (min_mode) st->launches[BFS_K_CONVERT] += 1;
+                    st->launches[BFS_K_CONVERT] += 1;
                 }
-            } else {
-                // nothing to expand: this level's slot stays zero -> search ends
-                HIP_TRY(T.begin());
-                launch_clear_words(L, slot, SLOT_WORDS);
-                HIP_TRY(hipGetLastError());
-                HIP_TRY(T.end(BFS_K_CONVERT, level));
             }
+            // with m_f == 0 nothing is launched: the slot was cleared by the
+            // previous level (or by init) and reads as an empty next frontier
         } else {
+            fmt_queue = false;
             HIP_TRY(T.begin());
-            launch_bu_sweep<OffT>(L, off, g->cols, fbits, nbits, visited, parent, depth, n, W, next_depth, serial,
-                                  slot, zslot);
+            launch_bu_sweep<OffT>(L, off, g->cols, fbits, nbits, visited, vprev, parent, depth, n, W, next_depth,
+                                  serial, slot, zslot);
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_BU_SWEEP, level));
             if (st) st->launches[BFS_K_BU_SWEEP] += 1;
@@ -281,17 +273,17 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
         m_f = m_next;
         if (cur_dir == 0) {
             qlen = (int64_t)h[S_QLEN];
+            qlen_dev = nullptr;
             int32_t* t = qcur; qcur = qnext; qnext = t;
-            fbits_fresh = false;
         } else {
             uint64_t* t = fbits; fbits = nbits; nbits = t;
-            fbits_fresh = true;
         }
         if (level > n + 1) return fail(BFS_E_HIP, "level loop did not terminate");
     }
     if (st) {
         st->levels = level;
         st->reached = reached;
+        st->isolated = g->isolated;
         st->edges_examined = examined;
         if (T.on) {
             HIP_TRY(hipStreamSynchronize(stream));
@@ -299,6 +291,21 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
         }
         st->total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     }
+    return BFS_OK;
+}
+
+template <typename OffT>
+bfs_status build_isolated(bfs_graph* g, hipStream_t s) {
+    const int64_t W = (g->n + 63) / 64;
+    HIP_TRY(hipMalloc((void**)&g->d_iso, sizeof(uint64_t) * (size_t)(W + 1)));
+    uint64_t* d_count = g->d_iso + W;
+    HIP_TRY(hipMemsetAsync(d_count, 0, sizeof(uint64_t), s));
+    Launch L{s, 4096};
+    launch_isolated_mask<OffT>(L, (const OffT*)g->off, g->n, W, g->d_iso, d_count);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(g->h_buf, d_count, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    g->isolated = (int64_t)g->h_buf[0];
     return BFS_OK;
 }
 
@@ -392,6 +399,15 @@ bfs_status bfs_create_graph_csr(int64_t n, const void* d_offsets, int offset_byt
             return bad;
         }
     }
+    // only in a symmetric graph is a vertex without row entries unreachable
+    if (n > 0 && (g->flags & BFS_GRAPH_SYMMETRIC)) {
+        bfs_status bs = g->off_bytes == 4 ? build_isolated<int32_t>(g, (hipStream_t)hip_stream)
+                                          : build_isolated<int64_t>(g, (hipStream_t)hip_stream);
+        if (bs != BFS_OK) {
+            bfs_destroy_graph(g);
+            return bs;
+        }
+    }
     *out = g;
     return BFS_OK;
 }
@@ -432,6 +448,7 @@ bfs_status bfs_create_graph_dcsc(int64_t nrows, int64_t ncols, int64_t row_base,
 void bfs_destroy_graph(bfs_graph* g) {
     if (!g) return;
     for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
+    if (g->d_iso) (void)hipFree(g->d_iso);
     if (g->h_buf) (void)hipHostFree(g->h_buf);
     delete g;
 }
@@ -456,6 +473,7 @@ bfs_status bfs_run(bfs_graph* g, int64_t source, const bfs_opts* opts, int32_t* 
     if (o.dir < BFS_DIR_DO || o.dir > BFS_DIR_BU) return fail(BFS_E_INVALID_ARG, "bad dir %d", o.dir);
     if (o.parent_mode != BFS_PARENT_ANY && o.parent_mode != BFS_PARENT_MIN)
         return fail(BFS_E_INVALID_ARG, "bad parent_mode %d", o.parent_mode);
+    if (o.td_claim != 0 && o.td_claim != 1) return fail(BFS_E_INVALID_ARG, "bad td_claim %d", o.td_claim);
     if (!(o.alpha > 0) || !(o.beta > 0)) return fail(BFS_E_INVALID_ARG, "alpha and beta must be > 0");
     if (source < 0 || source >= g->n)
         return fail(BFS_E_OUT_OF_RANGE, "source %lld outside [0, %lld)", (long long)source, (long long)g->n);

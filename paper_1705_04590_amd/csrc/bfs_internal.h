@@ -28,33 +28,42 @@ struct Launch {
     int grid_cap;   // workgroup cap for grid-stride kernels
 };
 
+// Top-down claim modes.
+enum { CLAIM_BITMAP = 0, CLAIM_CAS = 1, CLAIM_MIN = 2 };
+
 // ---- single source -------------------------------------------------------
-void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, uint64_t* visited, uint64_t* fbits,
-                 uint64_t* claim, int64_t W, int32_t* queue, int64_t src, uint64_t* counters);
+template <typename OffT>
+void launch_isolated_mask(const Launch& L, const OffT* off, int64_t n, int64_t W, uint64_t* iso, uint64_t* count);
+
+void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, uint64_t* visited, uint64_t* vprev,
+                 uint64_t* fbits, uint64_t* claim, const uint64_t* iso, int64_t W, int32_t* queue, int64_t src,
+                 uint64_t* counters);
 
 // degree prefix sum of the frontier queue + tile partition for the expand
 // (scan[i] = sum of degrees of q[0..i), tile_start[t] = queue index owning
-// edge t*TD_TILE, tile_start[ntiles] = qlen-1).  partial needs
-// ceil(qlen/SCAN_TILE)+1 int64.
+// edge t*TD_TILE, tile_start[ntiles] = qlen-1).  The queue length is read
+// from qlen_dev when it is not NULL (qlen_host is then an upper bound).
+// partial needs ceil(qlen_host/SCAN_TILE)+1 int64.
 template <typename OffT>
-int launch_td_scan(const Launch& L, const OffT* off, const int32_t* q, int64_t qlen, int64_t total, int64_t* scan,
-                   int32_t* tile_start, int64_t* partial);
+int launch_td_scan(const Launch& L, const OffT* off, const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host,
+                   int64_t total, int64_t* scan, int32_t* tile_start, int64_t* partial);
 
 template <typename OffT>
-void launch_td_expand(const Launch& L, bool min_mode, const OffT* off, const int32_t* cols, int64_t nnz,
-                      const int32_t* q, int64_t qlen, const int64_t* scan, const int32_t* tile_start, int64_t total,
-                      int32_t* parent, int32_t* depth, uint64_t* visited, uint64_t* claim, int32_t* qnext,
-                      uint64_t* slot, uint64_t* zslot, int32_t next_depth);
+void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t* cols, int64_t nnz,
+                      const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host, const int64_t* scan,
+                      const int32_t* tile_start, int64_t total, int32_t* parent, int32_t* depth,
+                      uint64_t* visited, uint64_t* claim, int32_t* qnext, uint64_t* slot, uint64_t* zslot,
+                      int32_t next_depth);
 
 template <typename OffT>
 void launch_bu_sweep(const Launch& L, const OffT* off, const int32_t* cols, const uint64_t* fbits, uint64_t* nbits,
-                     uint64_t* visited, int32_t* parent, int32_t* depth, int64_t n, int64_t W, int32_t next_depth,
-                     int serial_len, uint64_t* slot, uint64_t* zslot);
+                     uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t n, int64_t W,
+                     int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot);
 
 void launch_clear_words(const Launch& L, uint64_t* w, int64_t nw);
-void launch_queue_to_bitmap(const Launch& L, const int32_t* q, int64_t qlen, uint64_t* bits);
 void launch_bitmap_to_queue(const Launch& L, const uint64_t* bits, int64_t W, int32_t* q, uint64_t* qlen_ctr);
-void launch_merge_claim(const Launch& L, uint64_t* visited, uint64_t* claim, int64_t W);
+void launch_merge(const Launch& L, bool min_mode, uint64_t* visited, uint64_t* vprev, uint64_t* claim,
+                  uint64_t* fnext, int64_t W);
 
 template <typename OffT>
 void launch_validate_csr(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, int64_t nnz,

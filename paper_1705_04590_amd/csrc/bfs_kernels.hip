@@ -4,21 +4,28 @@
 //   a degree prefix sum over the frontier queue assigns every adjacency entry
 //   of the frontier a global index; fixed tiles of TD_TILE entries are then
 //   expanded by workgroups, each tile's frontier vertices staged in LDS, so a
-//   hub's row is spread over many workgroups.  A child is claimed with an
-//   atomic compare-and-swap on parent[] (ANY) or by atomicMin on parent[]
-//   plus an atomicOr claim bit (MIN, the (select2nd, min) semiring of
-//   Section 4.2).  Winners are compacted in LDS (wave ballot + mbcnt, one
-//   LDS atomic per wave) and appended to the next queue with one global
-//   atomicAdd per tile.
+//   hub's row is spread over many workgroups.  Each edge probes the visited
+//   bitmap once.  A child v is claimed by the one thread whose atomic
+//   fetch-or sets v's visited bit (CLAIM_BITMAP; the bitmap is n/8 bytes and
+//   lives in L2 / Infinity Cache) or whose compare-and-swap on parent[v]
+//   succeeds (CLAIM_CAS).  In MIN mode the visited bitmap stays frozen for
+//   the level, every frontier neighbour applies atomicMin to parent[v] (the
+//   (select2nd, min) semiring of Section 4.2) and a fetch-or on a separate
+//   claim bitmap picks the one thread that records depth and enqueues v.
+//   Winners are compacted in LDS (wave ballot + mbcnt, one LDS atomic per
+//   wave) and appended to the next queue with one global atomicAdd per tile.
+//   After the level one pass extracts the newly set bits as the next
+//   frontier bitmap.
 // Bottom-up level (Alg. 2; the local discovery of Alg. 4):
 //   one wave owns 64 consecutive vertices = one word of the visited bitmap.
-//   Fully visited words are skipped.  Each unvisited lane scans its sorted
-//   row serially for up to `serial_len` entries probing the frontier bitmap;
-//   rows still unresolved are then scanned by the whole wave 64 entries at a
-//   time, keeping the first hit in row order (the minimum-id parent).  The
-//   wave's ballot of found lanes is the next-frontier word and updates the
-//   visited word, so the sweep needs no atomics except three counters per
-//   workgroup.
+//   Vertices without edges are marked visited at initialisation, so words
+//   holding only visited or isolated vertices are skipped.  Each unvisited
+//   lane scans its sorted row for up to `serial_len` entries probing the
+//   frontier bitmap; rows still
+//   unresolved are then scanned by the whole wave 64 entries at a time,
+//   keeping the first hit in row order (the minimum-id parent).  The wave's
+//   ballot of found lanes is the next-frontier word and updates the visited
+//   word, so the sweep needs no atomics except three counters per workgroup.
 #include "bfs_internal.h"
 
 namespace bfsk {
@@ -70,9 +77,36 @@ static inline int grid_for(int64_t items, int per_block, int cap) {
 }
 
 // ------------------------------------------------------------------ init
+// isolated mask: bit set for vertices without entries and for ids >= n in
+// the last word; `count` receives the number of vertices without entries.
+template <typename OffT>
+__global__ __launch_bounds__(256) void k_isolated_mask(const OffT* __restrict__ off, int64_t n, int64_t W,
+                                                       uint64_t* __restrict__ iso, uint64_t* __restrict__ count) {
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (256 / WAVE);
+    uint64_t c = 0;
+    for (int64_t w = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE; w < W; w += nwaves) {
+        const int64_t v = w * WAVE + lane;
+        bool empty = true;
+        if (v < n) empty = off[v + 1] == off[v];
+        const uint64_t m = __ballot(empty);
+        if (lane == 0) iso[w] = m;
+        if (v < n && empty) c += 1;
+    }
+    c = wave_sum(c);
+    if (lane == 0 && c) atomicAdd((unsigned long long*)count, (unsigned long long)c);
+}
+
+template <typename OffT>
+void launch_isolated_mask(const Launch& L, const OffT* off, int64_t n, int64_t W, uint64_t* iso, uint64_t* count) {
+    hipLaunchKernelGGL(k_isolated_mask<OffT>, dim3(grid_for(W, 256 / WAVE, L.grid_cap)), dim3(256), 0, L.stream,
+                       off, n, W, iso, count);
+}
+
 __global__ void k_init(int32_t* __restrict__ parent, int32_t* __restrict__ depth, int64_t n,
-                       uint64_t* __restrict__ visited, uint64_t* __restrict__ fbits, uint64_t* __restrict__ claim,
-                       int64_t W, int32_t* __restrict__ queue, int64_t src, uint64_t* __restrict__ counters) {
+                       uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev, uint64_t* __restrict__ fbits,
+                       uint64_t* __restrict__ claim, const uint64_t* __restrict__ iso, int64_t W,
+                       int32_t* __restrict__ queue, int64_t src, uint64_t* __restrict__ counters) {
     int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = tid; v < n; v += stride) {
@@ -81,10 +115,13 @@ __global__ void k_init(int32_t* __restrict__ parent, int32_t* __restrict__ depth
         depth[v] = s ? 0 : -1;
     }
     for (int64_t w = tid; w < W; w += stride) {
+        // vertices without edges can never be reached: they start visited, and
         // ids >= n in the last word count as visited so its wave can finish
         uint64_t pad = (w == W - 1 && (n & 63)) ? (~0ull << (n & 63)) : 0ull;
         uint64_t sb = (w == (src >> 6)) ? (1ull << (src & 63)) : 0ull;
-        visited[w] = pad | sb;
+        const uint64_t vis = (iso ? iso[w] : pad) | sb;
+        visited[w] = vis;
+        vprev[w] = vis;
         fbits[w] = sb;
         claim[w] = 0;
     }
@@ -92,11 +129,12 @@ __global__ void k_init(int32_t* __restrict__ parent, int32_t* __restrict__ depth
     if (tid < SLOTS * SLOT_WORDS) counters[tid] = 0;
 }
 
-void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, uint64_t* visited, uint64_t* fbits,
-                 uint64_t* claim, int64_t W, int32_t* queue, int64_t src, uint64_t* counters) {
+void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, uint64_t* visited, uint64_t* vprev,
+                 uint64_t* fbits, uint64_t* claim, const uint64_t* iso, int64_t W, int32_t* queue, int64_t src,
+                 uint64_t* counters) {
     int g = grid_for(n > W ? n : W, 256, L.grid_cap * 4);
-    hipLaunchKernelGGL(k_init, dim3(g), dim3(256), 0, L.stream, parent, depth, n, visited, fbits, claim, W, queue,
-                       src, counters);
+    hipLaunchKernelGGL(k_init, dim3(g), dim3(256), 0, L.stream, parent, depth, n, visited, vprev, fbits, claim, iso,
+                       W, queue, src, counters);
 }
 
 // ------------------------------------------------------------------ frontier degree scan
@@ -107,11 +145,17 @@ __device__ __forceinline__ int64_t qdeg(const OffT* off, const int32_t* q, int64
 }
 
 // per-workgroup sums of SCAN_TILE queue entries' degrees
+__device__ __forceinline__ int64_t qlen_of(const uint64_t* qlen_dev, int64_t qlen_host) {
+    return qlen_dev ? (int64_t)*qlen_dev : qlen_host;
+}
+
 template <typename OffT>
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_partials(const OffT* __restrict__ off,
-                                                               const int32_t* __restrict__ q, int64_t qlen,
-                                                               int64_t* __restrict__ partial) {
+                                                               const int32_t* __restrict__ q,
+                                                               const uint64_t* __restrict__ qlen_dev,
+                                                               int64_t qlen_host, int64_t* __restrict__ partial) {
     __shared__ int64_t red[SCAN_BLOCK / WAVE];
+    const int64_t qlen = qlen_of(qlen_dev, qlen_host);
     int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
     int64_t s = 0;
     for (int k = 0; k < SCAN_IPT; ++k)
@@ -157,11 +201,13 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_top(int64_t* __restrict__ p
 // the entry whose edge range [scan[i], scan[i]+deg) holds t*TD_TILE owns tile t.
 template <typename OffT>
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const OffT* __restrict__ off,
-                                                            const int32_t* __restrict__ q, int64_t qlen,
+                                                            const int32_t* __restrict__ q,
+                                                            const uint64_t* __restrict__ qlen_dev, int64_t qlen_host,
                                                             const int64_t* __restrict__ partial, int64_t total,
                                                             int64_t ntiles, int64_t* __restrict__ scan,
                                                             int32_t* __restrict__ tile_start) {
     __shared__ int64_t wsum[SCAN_BLOCK / WAVE];
+    const int64_t qlen = qlen_of(qlen_dev, qlen_host);
     int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
     int64_t d[SCAN_IPT];
     int64_t s = 0;
@@ -198,28 +244,31 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const OffT* __restric
 }
 
 template <typename OffT>
-int launch_td_scan(const Launch& L, const OffT* off, const int32_t* q, int64_t qlen, int64_t total, int64_t* scan,
-                   int32_t* tile_start, int64_t* partial) {
-    int64_t nb = (qlen + SCAN_TILE - 1) / SCAN_TILE;
+int launch_td_scan(const Launch& L, const OffT* off, const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host,
+                   int64_t total, int64_t* scan, int32_t* tile_start, int64_t* partial) {
+    // qlen_host is exact when qlen_dev is NULL and an upper bound otherwise
+    int64_t nb = (qlen_host + SCAN_TILE - 1) / SCAN_TILE;
     int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
     int launches = 1;
     if (nb > 1) {
-        hipLaunchKernelGGL(k_scan_partials<OffT>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, L.stream, off, q, qlen,
-                           partial);
+        hipLaunchKernelGGL(k_scan_partials<OffT>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, L.stream, off, q,
+                           qlen_dev, qlen_host, partial);
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, L.stream, partial, nb);
         launches += 2;
     }
     hipLaunchKernelGGL(k_scan_apply<OffT>, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(SCAN_BLOCK), 0, L.stream, off,
-                       q, qlen, nb > 1 ? (const int64_t*)partial : nullptr, total, ntiles, scan, tile_start);
+                       q, qlen_dev, qlen_host, nb > 1 ? (const int64_t*)partial : nullptr, total, ntiles, scan,
+                       tile_start);
     return launches;
 }
 
 // ------------------------------------------------------------------ top-down expand
-template <typename OffT, bool MIN>
+template <typename OffT, int MODE>
 __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
     const OffT* __restrict__ off, const int32_t* __restrict__ cols, const int32_t* __restrict__ q,
-    const int64_t* __restrict__ scan, const int32_t* __restrict__ tile_start, int64_t qlen, int64_t total,
-    int64_t ntiles, int64_t nnz, int32_t* __restrict__ parent, int32_t* __restrict__ depth, uint64_t* __restrict__ visited,
+    const uint64_t* __restrict__ qlen_dev, int64_t qlen_host, const int64_t* __restrict__ scan,
+    const int32_t* __restrict__ tile_start, int64_t total, int64_t ntiles, int64_t nnz,
+    int32_t* __restrict__ parent, int32_t* __restrict__ depth, uint64_t* __restrict__ visited,
     uint64_t* __restrict__ claim, int32_t* __restrict__ qnext, uint64_t* __restrict__ slot,
     uint64_t* __restrict__ zslot, int32_t next_depth) {
     __shared__ int32_t s_start[TD_TILE + 1];   // first edge of staged vertex j, relative to the tile
@@ -230,6 +279,7 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
     __shared__ uint64_t s_qbase;
 
     if (blockIdx.x == 0 && threadIdx.x < SLOT_WORDS && zslot) zslot[threadIdx.x] = 0;
+    const int64_t qlen = qlen_of(qlen_dev, qlen_host);
     uint64_t my_n = 0, my_m = 0;
     const int lane = lane_id();
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -252,42 +302,69 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
         }
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
+        // the thread's TD_EPT edges move through each stage together so their
+        // loads and atomics are in flight at the same time
+        int32_t vv[TD_EPT], uu[TD_EPT];
+        bool cand[TD_EPT];
+#pragma unroll
         for (int k = 0; k < TD_EPT; ++k) {
             const int p = k * TD_BLOCK + threadIdx.x;
             const int64_t e = e0 + p;
-            bool won = false;
-            int32_t v = 0;
-            int64_t dv = 0;
-            if (e < e1 && nv > 0) {
+            cand[k] = e < e1 && nv > 0;
+            vv[k] = 0;
+            uu[k] = 0;
+            if (cand[k]) {
                 int lo = 0, hi = nv - 1;   // last staged vertex starting at or before p
                 while (lo < hi) {
                     int mid = (lo + hi + 1) >> 1;
                     if (s_start[mid] <= p) lo = mid; else hi = mid - 1;
                 }
-                const int32_t u = s_u[lo];
+                uu[k] = s_u[lo];
                 int64_t pos = s_base[lo] + e;
                 if (pos < 0 || pos >= nnz) pos = 0;   // unreachable for a consistent scan
-                v = cols[pos];
-                const uint64_t bit = 1ull << (v & 63);
-                if (!(visited[v >> 6] & bit)) {
-                    if (MIN) {
-                        atomicMin((unsigned int*)&parent[v], (unsigned int)u);
-                        uint64_t old = atomicOr((unsigned long long*)&claim[v >> 6], (unsigned long long)bit);
-                        won = !(old & bit);
-                    } else {
-                        won = atomicCAS(&parent[v], -1, u) == -1;
-                        if (won) atomicOr((unsigned long long*)&visited[v >> 6], (unsigned long long)bit);
-                    }
-                }
-                if (won) {
-                    depth[v] = next_depth;
-                    dv = (int64_t)off[v + 1] - (int64_t)off[v];
-                    my_n += 1;
-                    my_m += (uint64_t)dv;
+                vv[k] = cols[pos];
+            }
+        }
+        // one probe of the visited bitmap per edge; ANY modes claim on that
+        // same bitmap, MIN mode keeps it frozen for the level and claims on
+        // a separate bitmap (all frontier neighbours must reach atomicMin)
+        uint64_t vw[TD_EPT];
+#pragma unroll
+        for (int k = 0; k < TD_EPT; ++k) vw[k] = cand[k] ? visited[vv[k] >> 6] : ~0ull;
+        bool won[TD_EPT];
+#pragma unroll
+        for (int k = 0; k < TD_EPT; ++k) {
+            const int32_t v = vv[k];
+            const uint64_t bit = 1ull << (v & 63);
+            won[k] = false;
+            if (!(vw[k] & bit)) {
+                if (MODE == CLAIM_MIN) {
+                    // every frontier neighbour offers itself; the smallest id stays
+                    atomicMin((unsigned int*)&parent[v], (unsigned int)uu[k]);
+                    const uint64_t old = atomicOr((unsigned long long*)&claim[v >> 6], (unsigned long long)bit);
+                    won[k] = !(old & bit);
+                } else if (MODE == CLAIM_CAS) {
+                    won[k] = atomicCAS(&parent[v], -1, uu[k]) == -1;
+                    if (won[k]) atomicOr((unsigned long long*)&visited[v >> 6], (unsigned long long)bit);
+                } else {
+                    const uint64_t old = atomicOr((unsigned long long*)&visited[v >> 6], (unsigned long long)bit);
+                    won[k] = !(old & bit);
+                    if (won[k]) parent[v] = uu[k];
                 }
             }
+        }
+#pragma unroll
+        for (int k = 0; k < TD_EPT; ++k) {
+            const int32_t v = vv[k];
+            int64_t dv = 0;
+            if (won[k]) {
+                depth[v] = next_depth;
+                dv = (int64_t)off[v + 1] - (int64_t)off[v];
+                my_n += 1;
+                my_m += (uint64_t)dv;
+            }
             // vertices without out-edges are discovered but never expanded
-            const bool push = won && dv > 0;
+            const bool push = won[k] && dv > 0;
             const uint64_t wm = __ballot(push);
             if (wm) {
                 const int leader = __ffsll((unsigned long long)wm) - 1;
@@ -309,27 +386,29 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
 }
 
 template <typename OffT>
-void launch_td_expand(const Launch& L, bool min_mode, const OffT* off, const int32_t* cols, int64_t nnz,
-                      const int32_t* q, int64_t qlen, const int64_t* scan, const int32_t* tile_start, int64_t total,
-                      int32_t* parent, int32_t* depth, uint64_t* visited, uint64_t* claim, int32_t* qnext,
-                      uint64_t* slot, uint64_t* zslot, int32_t next_depth) {
+void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t* cols, int64_t nnz,
+                      const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host, const int64_t* scan,
+                      const int32_t* tile_start, int64_t total, int32_t* parent, int32_t* depth,
+                      uint64_t* visited, uint64_t* claim, int32_t* qnext, uint64_t* slot, uint64_t* zslot,
+                      int32_t next_depth) {
     int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
     int g = grid_for(ntiles, 1, L.grid_cap);
-    if (min_mode)
-        hipLaunchKernelGGL((k_td_expand<OffT, true>), dim3(g), dim3(TD_BLOCK), 0, L.stream, off, cols, q, scan,
-                           tile_start, qlen, total, ntiles, nnz, parent, depth, visited, claim, qnext, slot,
-                           zslot, next_depth);
-    else
-        hipLaunchKernelGGL((k_td_expand<OffT, false>), dim3(g), dim3(TD_BLOCK), 0, L.stream, off, cols, q, scan,
-                           tile_start, qlen, total, ntiles, nnz, parent, depth, visited, claim, qnext, slot,
-                           zslot, next_depth);
+#define BFS_EXPAND(M)                                                                                        \
+    hipLaunchKernelGGL((k_td_expand<OffT, M>), dim3(g), dim3(TD_BLOCK), 0, L.stream, off, cols, q, qlen_dev, \
+                       qlen_host, scan, tile_start, total, ntiles, nnz, parent, depth, visited, claim, qnext,  \
+                       slot, zslot, next_depth)
+    if (mode == CLAIM_MIN) BFS_EXPAND(CLAIM_MIN);
+    else if (mode == CLAIM_CAS) BFS_EXPAND(CLAIM_CAS);
+    else BFS_EXPAND(CLAIM_BITMAP);
+#undef BFS_EXPAND
 }
 
 // ------------------------------------------------------------------ bottom-up sweep
 template <typename OffT>
 __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
     const OffT* __restrict__ off, const int32_t* __restrict__ cols, const uint64_t* __restrict__ fbits,
-    uint64_t* __restrict__ nbits, uint64_t* __restrict__ visited, int32_t* __restrict__ parent,
+    uint64_t* __restrict__ nbits, uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev,
+    int32_t* __restrict__ parent,
     int32_t* __restrict__ depth, int64_t n, int64_t W, int32_t next_depth, int serial_len,
     uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot) {
     if (blockIdx.x == 0 && threadIdx.x < SLOT_WORDS && zslot) zslot[threadIdx.x] = 0;
@@ -352,6 +431,8 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
         int64_t p = beg;
         const int64_t lim = (end - beg > serial_len) ? beg + serial_len : end;
         int32_t par = -1;
+        // one probe per step: most rows hit within the first two entries, and
+        // every probe moves a line of the frontier bitmap
         while (p < lim) {
             const int32_t c = cols[p];
             if ((fbits[c >> 6] >> (c & 63)) & 1ull) { par = c; break; }
@@ -389,7 +470,10 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
         const uint64_t fm = __ballot(found);
         if (lane == 0) {
             nbits[w] = fm;
-            if (fm) visited[w] = vis | fm;
+            if (fm) {
+                visited[w] = vis | fm;
+                vprev[w] = vis | fm;
+            }
         }
         if (found) {
             parent[v] = par;
@@ -406,11 +490,11 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
 
 template <typename OffT>
 void launch_bu_sweep(const Launch& L, const OffT* off, const int32_t* cols, const uint64_t* fbits, uint64_t* nbits,
-                     uint64_t* visited, int32_t* parent, int32_t* depth, int64_t n, int64_t W, int32_t next_depth,
-                     int serial_len, uint64_t* slot, uint64_t* zslot) {
+                     uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t n, int64_t W,
+                     int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot) {
     int g = grid_for(W, BU_BLOCK / WAVE, L.grid_cap);
     hipLaunchKernelGGL(k_bu_sweep<OffT>, dim3(g), dim3(BU_BLOCK), 0, L.stream, off, cols, fbits, nbits, visited,
-                       parent, depth, n, W, next_depth, serial_len, slot, zslot);
+                       vprev, parent, depth, n, W, next_depth, serial_len, slot, zslot);
 }
 
 // ------------------------------------------------------------------ conversions
@@ -421,19 +505,6 @@ __global__ void k_clear_words(uint64_t* __restrict__ w, int64_t nw) {
 
 void launch_clear_words(const Launch& L, uint64_t* w, int64_t nw) {
     hipLaunchKernelGGL(k_clear_words, dim3(grid_for(nw, 256, L.grid_cap * 4)), dim3(256), 0, L.stream, w, nw);
-}
-
-__global__ void k_queue_to_bitmap(const int32_t* __restrict__ q, int64_t qlen, uint64_t* __restrict__ bits) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < qlen; i += stride) {
-        int32_t v = q[i];
-        atomicOr((unsigned long long*)&bits[v >> 6], 1ull << (v & 63));
-    }
-}
-
-void launch_queue_to_bitmap(const Launch& L, const int32_t* q, int64_t qlen, uint64_t* bits) {
-    hipLaunchKernelGGL(k_queue_to_bitmap, dim3(grid_for(qlen, 256, L.grid_cap * 4)), dim3(256), 0, L.stream, q,
-                       qlen, bits);
 }
 
 // one word per thread; workgroup-wide exclusive scan of popcounts gives each
@@ -471,20 +542,43 @@ void launch_bitmap_to_queue(const Launch& L, const uint64_t* bits, int64_t W, in
                        qlen_ctr);
 }
 
-__global__ void k_merge_claim(uint64_t* __restrict__ visited, uint64_t* __restrict__ claim, int64_t W) {
+// after a top-down level the bits that became set are the next frontier.
+// ANY modes claimed on visited itself: next = visited & ~vprev.  MIN mode
+// claimed on `claim`: next = claim, folded into visited and cleared.  Both
+// leave vprev == visited for the next level.
+__global__ void k_merge_any(const uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev,
+                            uint64_t* __restrict__ fnext, int64_t W) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < W; i += stride) {
-        uint64_t c = claim[i];
+        const uint64_t v = visited[i], p = vprev[i];
+        fnext[i] = v & ~p;
+        if (v != p) vprev[i] = v;
+    }
+}
+
+__global__ void k_merge_claim(uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev,
+                              uint64_t* __restrict__ claim, uint64_t* __restrict__ fnext, int64_t W) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < W; i += stride) {
+        const uint64_t c = claim[i];
+        fnext[i] = c;
         if (c) {
-            visited[i] |= c;
+            const uint64_t v = visited[i] | c;
+            visited[i] = v;
+            vprev[i] = v;
             claim[i] = 0;
         }
     }
 }
 
-void launch_merge_claim(const Launch& L, uint64_t* visited, uint64_t* claim, int64_t W) {
-    hipLaunchKernelGGL(k_merge_claim, dim3(grid_for(W, 256, L.grid_cap * 4)), dim3(256), 0, L.stream, visited,
-                       claim, W);
+void launch_merge(const Launch& L, bool min_mode, uint64_t* visited, uint64_t* vprev, uint64_t* claim,
+                  uint64_t* fnext, int64_t W) {
+    if (min_mode)
+        hipLaunchKernelGGL(k_merge_claim, dim3(grid_for(W, 256, L.grid_cap * 4)), dim3(256), 0, L.stream, visited,
+                           vprev, claim, fnext, W);
+    else
+        hipLaunchKernelGGL(k_merge_any, dim3(grid_for(W, 256, L.grid_cap * 4)), dim3(256), 0, L.stream, visited,
+                           vprev, fnext, W);
 }
 
 // ------------------------------------------------------------------ validation
@@ -533,14 +627,16 @@ void launch_validate_csr(const Launch& L, const OffT* off, const int32_t* cols, 
 
 // ------------------------------------------------------------------ instantiations
 #define BFS_INST(T)                                                                                              \
-    template int launch_td_scan<T>(const Launch&, const T*, const int32_t*, int64_t, int64_t, int64_t*,        \
-                                   int32_t*, int64_t*);                                                         \
-    template void launch_td_expand<T>(const Launch&, bool, const T*, const int32_t*, int64_t, const int32_t*, \
-                                      int64_t, const int64_t*, const int32_t*, int64_t, int32_t*, int32_t*,     \
-                                      uint64_t*, uint64_t*, int32_t*, uint64_t*, uint64_t*, int32_t);            \
+    template void launch_isolated_mask<T>(const Launch&, const T*, int64_t, int64_t, uint64_t*, uint64_t*);      \
+    template int launch_td_scan<T>(const Launch&, const T*, const int32_t*, const uint64_t*, int64_t, int64_t,  \
+                                   int64_t*, int32_t*, int64_t*);                                               \
+    template void launch_td_expand<T>(const Launch&, int, const T*, const int32_t*, int64_t, const int32_t*,   \
+                                      const uint64_t*, int64_t, const int64_t*, const int32_t*, int64_t,        \
+                                      int32_t*, int32_t*, uint64_t*, uint64_t*, int32_t*, uint64_t*,            \
+                                      uint64_t*, int32_t);                                                      \
     template void launch_bu_sweep<T>(const Launch&, const T*, const int32_t*, const uint64_t*, uint64_t*,      \
-                                     uint64_t*, int32_t*, int32_t*, int64_t, int64_t, int32_t, int, uint64_t*,  \
-                                     uint64_t*);                                                                \
+                                     uint64_t*, uint64_t*, int32_t*, int32_t*, int64_t, int64_t, int32_t, int,  \
+                                     uint64_t*, uint64_t*);                                                     \
     template void launch_validate_csr<T>(const Launch&, const T*, const int32_t*, int64_t, int64_t, uint32_t,  \
                                          uint32_t*);
 BFS_INST(int32_t)

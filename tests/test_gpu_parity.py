@@ -118,10 +118,11 @@ def test_parity_all_modes(orc, graphs, name, direction):
         dg = get(graphs, name, off_dtype)
         for s in sources_for(dg.off):
             ref = orc.bfs_min(dg.off, dg.cols, int(s))
-            for pm in (bfs.BFS_PARENT_ANY, bfs.BFS_PARENT_MIN):
-                p, d, st = dg.run(s, dir=dirv, parent_mode=pm)
+            for pm, claim in ((bfs.BFS_PARENT_ANY, 0), (bfs.BFS_PARENT_ANY, 1), (bfs.BFS_PARENT_MIN, 0)):
+                p, d, st = dg.run(s, dir=dirv, parent_mode=pm, td_claim=claim)
                 check(orc, dg, s, p, d, pm == bfs.BFS_PARENT_MIN, ref)
                 assert st.reached == int((d >= 0).sum())
+                assert st.isolated == int((np.diff(dg.off) == 0).sum())
 
 
 @pytest.mark.parametrize("name", ["kron12", "kron14", "grid", "pieces"])
@@ -262,3 +263,37 @@ def test_config2_scale22_sampled_sources(orc):
         for pm in (bfs.BFS_PARENT_ANY, bfs.BFS_PARENT_MIN):
             p, d, _ = dg.run(s, parent_mode=pm)
             check(orc, dg, s, p, d, pm == bfs.BFS_PARENT_MIN, ref)
+
+
+def _progress(msg):
+    import sys
+    import time
+    print(f"[{time.strftime('%H:%M:%S')}] {msg}", file=sys.__stderr__, flush=True)
+
+
+def test_config3_scale26_full_size(orc):
+    """Kronecker scale 26 (the benchmark workload, default launch configuration).
+
+    One source compared exactly (depths and minimum-id parents, the oracle run
+    on the CPU); a second source checked through the BFS-tree invariants,
+    which pin the depths exactly at any size.
+    """
+    _progress("scale 26: generating")
+    off, cols = graphgen.kronecker(26, seed=1)
+    _progress("scale 26: to device")
+    dg = DevGraph(off, cols, np.int64, flags=bfs.BFS_GRAPH_SYMMETRIC | bfs.BFS_GRAPH_SORTED)
+    srcs = graphgen.random_sources(off, 64, seed=2)
+    s = int(srcs[0])
+    _progress("scale 26: oracle")
+    ref = orc.bfs_min(off, cols, s)
+    _progress("scale 26: GPU min parents")
+    p, d, st = dg.run(s, parent_mode=bfs.BFS_PARENT_MIN)
+    check(orc, dg, s, p, d, True, ref)
+    assert st.bu_levels > 0 and st.td_levels > 0
+    del ref
+    s = int(srcs[1])
+    _progress("scale 26: GPU any parents + validator")
+    p, d, _ = dg.run(s, parent_mode=bfs.BFS_PARENT_ANY)
+    res = orc.validate(off, cols, s, p, d)
+    assert res[0] == "ok", res
+    _progress("scale 26: done")

@@ -339,8 +339,8 @@ MUTANTS = [
      "                }\n            }\n        }\n        unsigned char* t", "exhaustive"),
     ("if (inf[ecol[e]] && col_base + ecol[e] < best[erow[e]])", "if (inf[ecol[e]] && col_base + ecol[e] > best[erow[e]] - 1)", "fig2"),
     ("if ((completed[r >> 6] >> (r & 63)) & 1ULL) continue;", "", "fig2"),
-    ("if (!row_contains(off, cols, u, (int32_t)v))", "if (0)", "validator"),
-    ("if (depth[v] > depth[u] + 1) { *bad_vertex = v; return V_SKIP; }", "", "validator"),
+    ("if (parent[v] == (int32_t)u) edge_ok[v] = 1;", "edge_ok[v] = 1;", "validator"),
+    ("if (depth[v] > depth[u] + 1) { *bad_vertex = v; code = V_SKIP; break; }", "", "validator"),
 ]
 
 
