@@ -204,6 +204,12 @@ bfs_status bfs_run_multi(bfs_graph* g, const int64_t* h_sources, int k, const bf
                          int32_t* d_depth, void* d_workspace, size_t workspace_bytes, void* hip_stream,
                          bfs_stats* stats);
 
+/* Block workspace: bfs_workspace_bytes(g, 1) bytes, 256-B aligned, shared by
+ * bfs_block_td and bfs_block_bu.  It must be zero-filled before its first
+ * use; every successful call leaves its accumulator zeroed again (a failed
+ * or interrupted call requires zero-filling it anew).  Calls that share one
+ * workspace must be ordered (same stream).                                  */
+
 /* Top-down local discovery on a DCSC block (Alg. 3, the SpMSV on the
  * (select2nd, min) semiring of Section 4.2): for every block row r with an
  * entry in a frontier column, parent(r) = min(col_base + k) over frontier

@@ -183,23 +183,27 @@ def bfs_create_graph_csr(offsets: torch.Tensor, cols: torch.Tensor, flags: int =
     return Graph(h, (offsets, cols), "csr", n=n, nnz=cols.numel(), flags=flags)
 
 
+def _opt_ptr(t, dtype, name, numel=None):
+    if t is None or t.numel() == 0:
+        return None
+    return _dev(t, dtype, name, numel)
+
+
 def bfs_create_graph_dcsc(nrows: int, ncols: int, row_base: int, col_base: int, jc, cp, ir, jr=None, rp=None,
                           ic=None, flags: int = 0, stream=None) -> Graph:
-    nzc = jc.numel()
-    nnz = ir.numel()
-    pjc = _dev(jc, torch.int32, "jc") if nzc else 0
+    """Wrap a DCSC block (jc, cp, ir) and optionally its row-compressed copy (jr, rp, ic)."""
+    nzc, nnz = jc.numel(), ir.numel()
     pcp = _dev(cp, torch.int64, "cp", nzc + 1)
-    pir = _dev(ir, torch.int32, "ir") if nnz else 0
-    nzr, pjr, prp, pic = 0, None, None, None
+    nzr, prp = 0, None
     if jr is not None:
         nzr = jr.numel()
-        pjr = _dev(jr, torch.int32, "jr") if nzr else rp.data_ptr()
         prp = _dev(rp, torch.int64, "rp", nzr + 1)
-        pic = _dev(ic, torch.int32, "ic") if nnz else 0
     h = _vp()
-    _check(lib().bfs_create_graph_dcsc(nrows, ncols, row_base, col_base, nzc, pjc or pcp, pcp, pir or pcp, nzr,
-                                       pjr, prp, pic or (prp if pjr else None), nnz, flags, _stream(stream),
-                                       ctypes.byref(h)), "bfs_create_graph_dcsc")
+    _check(lib().bfs_create_graph_dcsc(nrows, ncols, row_base, col_base, nzc, _opt_ptr(jc, torch.int32, "jc"), pcp,
+                                       _opt_ptr(ir, torch.int32, "ir"), nzr,
+                                       _opt_ptr(jr, torch.int32, "jr") if jr is not None else None,
+                                       prp, _opt_ptr(ic, torch.int32, "ic") if ic is not None else None, nnz, flags,
+                                       _stream(stream), ctypes.byref(h)), "bfs_create_graph_dcsc")
     return Graph(h, (jc, cp, ir, jr, rp, ic), "dcsc", nrows=nrows, ncols=ncols, row_base=row_base,
                  col_base=col_base, nnz=nnz, flags=flags)
 
@@ -213,10 +217,13 @@ def bfs_workspace_bytes(g: Graph, k: int = 1) -> int:
 
 
 def workspace(g: Graph, k: int = 1, device=None) -> torch.Tensor:
-    """A device byte tensor large enough for bfs_run (k=1), bfs_run_multi (k) or the block calls."""
+    """A device byte tensor large enough for bfs_run (k=1), bfs_run_multi (k) or the block calls
+    (zero-filled, as the block calls require before first use)."""
     nb = bfs_workspace_bytes(g, k)
     if nb == 0:
         raise BfsError(1, "bfs_workspace_bytes", f"no workspace size for k={k}")
+    if g.kind == "dcsc":
+        return torch.zeros(nb, dtype=torch.uint8, device=device or "cuda")
     return torch.empty(nb, dtype=torch.uint8, device=device or "cuda")
 
 
@@ -246,17 +253,21 @@ def bfs_run_multi(g: Graph, sources, parent: torch.Tensor | None, depth: torch.T
 
 def bfs_block_td(g: Graph, frontier: torch.Tensor, out_rows: torch.Tensor, out_parents: torch.Tensor,
                  nout: torch.Tensor, ws: torch.Tensor, stream=None):
+    """Alg. 3 local discovery on a DCSC block (asynchronous). ws must be zero-filled before its first use."""
     nf = frontier.numel()
-    pf = _dev(frontier, torch.int32, "frontier") if nf else _dev(nout, torch.int64, "nout")
-    _check(lib().bfs_block_td(g.handle, pf, nf, _dev(out_rows, torch.int32, "out_rows", g.nrows),
-                              _dev(out_parents, torch.int32, "out_parents", g.nrows), _dev(nout, torch.int64, "nout", 1),
-                              _dev(ws, torch.uint8, "workspace"), ws.numel(), _stream(stream)), "bfs_block_td")
+    _check(lib().bfs_block_td(g.handle, _opt_ptr(frontier, torch.int32, "frontier"), nf,
+                              _dev(out_rows, torch.int32, "out_rows", g.nrows),
+                              _dev(out_parents, torch.int32, "out_parents", g.nrows),
+                              _dev(nout, torch.int64, "nout", 1), _dev(ws, torch.uint8, "workspace"), ws.numel(),
+                              _stream(stream)), "bfs_block_td")
 
 
 def bfs_block_bu(g: Graph, fbits: torch.Tensor, completed: torch.Tensor, row_lo: int, row_hi: int,
                  out_rows: torch.Tensor, out_parents: torch.Tensor, nout: torch.Tensor, ws: torch.Tensor, stream=None):
+    """Alg. 4 local discovery sub-step on a DCSC block (asynchronous); bitmaps are int64 tensors of words."""
     _check(lib().bfs_block_bu(g.handle, _dev(fbits, torch.int64, "fbits", (g.ncols + 63) // 64),
                               _dev(completed, torch.int64, "completed", (g.nrows + 63) // 64), row_lo, row_hi,
                               _dev(out_rows, torch.int32, "out_rows", g.nrows),
-                              _dev(out_parents, torch.int32, "out_parents", g.nrows), _dev(nout, torch.int64, "nout", 1),
-                              _dev(ws, torch.uint8, "workspace"), ws.numel(), _stream(stream)), "bfs_block_bu")
+                              _dev(out_parents, torch.int32, "out_parents", g.nrows),
+                              _dev(nout, torch.int64, "nout", 1), _dev(ws, torch.uint8, "workspace"), ws.numel(),
+                              _stream(stream)), "bfs_block_bu")

@@ -98,6 +98,60 @@ SingleLayout single_layout(const bfs_graph* g) {
     return L;
 }
 
+struct BlockLayout {
+    size_t header, q, scan, tiles, partial, spa, occ, bpar, bmask, total;
+};
+
+BlockLayout block_layout(const bfs_graph* g) {
+    BlockLayout L{};
+    const int64_t qmax = g->ncols < g->nzc ? g->ncols : g->nzc;
+    const int64_t wr = (g->nrows + 63) / 64;
+    const int64_t chunks = (g->nzr + 63) / 64;
+    int64_t scan_len = g->ncols;
+    if (wr > scan_len) scan_len = wr;
+    if (chunks > scan_len) scan_len = chunks;
+    size_t o = 0;
+    L.header = o; o = align_up(o + sizeof(uint64_t) * 8);
+    L.q = o; o = align_up(o + sizeof(int32_t) * (size_t)(qmax + 1));
+    L.scan = o; o = align_up(o + sizeof(int64_t) * (size_t)(qmax + 2));
+    L.tiles = o; o = align_up(o + sizeof(int32_t) * (size_t)((g->nnz + TD_TILE - 1) / TD_TILE + 2));
+    L.partial = o; o = align_up(o + sizeof(int64_t) * (size_t)((scan_len + SCAN_TILE - 1) / SCAN_TILE + 2));
+    L.spa = o; o = align_up(o + sizeof(uint32_t) * (size_t)g->nrows);
+    L.occ = o; o = align_up(o + sizeof(uint64_t) * (size_t)wr);
+    L.bpar = o; o = align_up(o + sizeof(int32_t) * (size_t)(chunks * 64 + 1));
+    L.bmask = o; o = align_up(o + sizeof(uint64_t) * (size_t)(chunks + 1));
+    L.total = o;
+    return L;
+}
+
+BlockWs block_ws(const bfs_graph* g, char* ws) {
+    const BlockLayout Lo = block_layout(g);
+    BlockWs W{};
+    W.header = (uint64_t*)(ws + Lo.header);
+    W.qlen = W.header;
+    W.total = (int64_t*)(W.header + 1);
+    W.range = W.header + 2;
+    W.q = (int32_t*)(ws + Lo.q);
+    W.scan = (int64_t*)(ws + Lo.scan);
+    W.tiles = (int32_t*)(ws + Lo.tiles);
+    W.partial = (int64_t*)(ws + Lo.partial);
+    W.spa = (uint32_t*)(ws + Lo.spa);
+    W.occ = (uint64_t*)(ws + Lo.occ);
+    W.bpar = (int32_t*)(ws + Lo.bpar);
+    W.bmask = (uint64_t*)(ws + Lo.bmask);
+    return W;
+}
+
+BlockArgs block_args(const bfs_graph* g) {
+    BlockArgs B{};
+    B.nrows = g->nrows; B.ncols = g->ncols; B.col_base = g->col_base;
+    B.nzc = g->nzc; B.nzr = g->nzr; B.nnz = g->nnz;
+    B.jc = g->jc; B.ir = g->ir; B.jr = g->jr; B.ic = g->ic; B.cp = g->cp; B.rp = g->rp;
+    return B;
+}
+
+size_t multi_bytes(const bfs_graph*, int) { return 0; }
+
 // -------------------------------------------------------------- timing
 struct Timer {
     bfs_graph* g;
@@ -218,7 +272,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
         if (cur_dir == 0) {
             if (m_f > 0) {
                 HIP_TRY(T.begin());
-                int nl = launch_td_scan<OffT>(L, off, qcur, qlen_dev, qlen, m_f, scan, tiles, partial);
+                int nl = launch_td_scan<OffT>(L, off, qcur, qlen_dev, qlen, scan, tiles, partial, nullptr);
                 HIP_TRY(hipGetLastError());
                 HIP_TRY(T.end(BFS_K_TD_SCAN, level));
                 HIP_TRY(T.begin());
@@ -441,6 +495,36 @@ bfs_status bfs_create_graph_dcsc(int64_t nrows, int64_t ncols, int64_t row_base,
         delete g;
         return fail(BFS_E_HIP, "create: %s", hipGetErrorString(e));
     }
+    if (flags & BFS_GRAPH_VALIDATE) {
+        hipStream_t s = (hipStream_t)hip_stream;
+        uint32_t* d_err = nullptr;
+        e = hipMalloc((void**)&d_err, sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMemsetAsync(d_err, 0, sizeof(uint32_t), s);
+        if (e == hipSuccess) {
+            Launch L{s, 4096};
+            const bool sorted = (g->flags & BFS_GRAPH_SORTED) != 0;
+            launch_validate_dcs(L, d_jc, d_cp, d_ir, nzc, ncols, nrows, nnz, sorted, d_err);
+            if (d_jr) launch_validate_dcs(L, d_jr, d_rp, d_ic, nzr, nrows, ncols, nnz, sorted, d_err);
+            e = hipGetLastError();
+        }
+        uint32_t herr = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&herr, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(s);
+        if (d_err) (void)hipFree(d_err);
+        if (e != hipSuccess) {
+            bfs_destroy_graph(g);
+            return fail(BFS_E_HIP, "validation: %s", hipGetErrorString(e));
+        }
+        bfs_status bad = BFS_OK;
+        if (herr & VE_OFFSETS) bad = fail(BFS_E_INVALID_ARG, "pointers not monotone or not ending at nnz");
+        else if (herr & VE_RANGE) bad = fail(BFS_E_OUT_OF_RANGE, "an id is out of range or the ids are not ascending");
+        else if (herr & VE_UNSORTED) bad = fail(BFS_E_UNSORTED, "a column (row) is not ascending");
+        if (bad != BFS_OK) {
+            bfs_destroy_graph(g);
+            return bad;
+        }
+    }
     *out = g;
     return BFS_OK;
 }
@@ -458,8 +542,9 @@ size_t bfs_workspace_bytes(const bfs_graph* g, int k) {
     if (g->kind == KIND_CSR) {
         if (k < 1 || k > 64) return 0;
         if (k == 1) return single_layout(g).total;
-        return 0;
+        return multi_bytes(g, k);
     }
+    if (g->kind == KIND_DCSC) return block_layout(g).total;
     return 0;
 }
 
@@ -510,17 +595,47 @@ bfs_status bfs_run_multi(bfs_graph* g, const int64_t* h_sources, int k, const bf
 bfs_status bfs_block_td(bfs_graph* g, const int32_t* d_frontier, int64_t nf, int32_t* d_out_rows,
                         int32_t* d_out_parents, int64_t* d_nout, void* d_workspace, size_t workspace_bytes,
                         void* hip_stream) {
-    (void)g; (void)d_frontier; (void)nf; (void)d_out_rows; (void)d_out_parents; (void)d_nout; (void)d_workspace;
-    (void)workspace_bytes; (void)hip_stream;
-    return fail(BFS_E_UNSUPPORTED, "bfs_block_td is not built yet");
+    if (!g || g->kind != KIND_DCSC) return fail(BFS_E_INVALID_ARG, "graph handle is not a DCSC block");
+    if (nf < 0 || nf > g->ncols) return fail(BFS_E_INVALID_ARG, "nf=%lld outside [0, ncols]", (long long)nf);
+    if ((nf > 0 && !d_frontier) || !d_out_rows || !d_out_parents || !d_nout || !d_workspace)
+        return fail(BFS_E_INVALID_ARG, "NULL frontier, output or workspace");
+    if ((uintptr_t)d_workspace % ALIGN) return fail(BFS_E_INVALID_ARG, "workspace not 256-byte aligned");
+    const BlockLayout Lo = block_layout(g);
+    if (workspace_bytes < Lo.total)
+        return fail(BFS_E_BUDGET, "workspace %zu < %zu bytes", workspace_bytes, Lo.total);
+    hipStream_t st = (hipStream_t)hip_stream;
+    Launch L{st, 2048};
+    const BlockWs W = block_ws(g, (char*)d_workspace);
+    launch_clear_words(L, W.header, 8);
+    launch_block_td(L, block_args(g), d_frontier, nf, d_out_rows, d_out_parents, d_nout, W);
+    HIP_TRY(hipGetLastError());
+    return BFS_OK;
 }
 
 bfs_status bfs_block_bu(bfs_graph* g, const uint64_t* d_fbits, uint64_t* d_completed, int64_t row_lo,
                         int64_t row_hi, int32_t* d_out_rows, int32_t* d_out_parents, int64_t* d_nout,
                         void* d_workspace, size_t workspace_bytes, void* hip_stream) {
-    (void)g; (void)d_fbits; (void)d_completed; (void)row_lo; (void)row_hi; (void)d_out_rows; (void)d_out_parents;
-    (void)d_nout; (void)d_workspace; (void)workspace_bytes; (void)hip_stream;
-    return fail(BFS_E_UNSUPPORTED, "bfs_block_bu is not built yet");
+    if (!g || g->kind != KIND_DCSC) return fail(BFS_E_INVALID_ARG, "graph handle is not a DCSC block");
+    if (!g->jr) return fail(BFS_E_UNSUPPORTED, "the block was created without its row-major copy");
+    if (!(g->flags & BFS_GRAPH_SORTED))
+        return fail(BFS_E_UNSUPPORTED, "a first-hit row scan needs ascending rows: create with BFS_GRAPH_SORTED");
+    if (row_lo < 0 || row_hi > g->nrows || row_lo > row_hi)
+        return fail(BFS_E_INVALID_ARG, "row range [%lld, %lld) outside [0, %lld]", (long long)row_lo,
+                    (long long)row_hi, (long long)g->nrows);
+    if (!d_fbits || !d_completed || !d_out_rows || !d_out_parents || !d_nout || !d_workspace)
+        return fail(BFS_E_INVALID_ARG, "NULL bitmap, output or workspace");
+    if ((uintptr_t)d_workspace % ALIGN) return fail(BFS_E_INVALID_ARG, "workspace not 256-byte aligned");
+    const BlockLayout Lo = block_layout(g);
+    if (workspace_bytes < Lo.total)
+        return fail(BFS_E_BUDGET, "workspace %zu < %zu bytes", workspace_bytes, Lo.total);
+    hipStream_t st = (hipStream_t)hip_stream;
+    Launch L{st, 2048};
+    const BlockWs W = block_ws(g, (char*)d_workspace);
+    launch_clear_words(L, W.header, 8);
+    launch_block_bu(L, block_args(g), d_fbits, d_completed, row_lo, row_hi, 16, d_out_rows, d_out_parents,
+                    d_nout, W);
+    HIP_TRY(hipGetLastError());
+    return BFS_OK;
 }
 
 }  // extern "C"

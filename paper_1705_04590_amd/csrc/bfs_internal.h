@@ -43,10 +43,11 @@ void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, ui
 // (scan[i] = sum of degrees of q[0..i), tile_start[t] = queue index owning
 // edge t*TD_TILE, tile_start[ntiles] = qlen-1).  The queue length is read
 // from qlen_dev when it is not NULL (qlen_host is then an upper bound).
-// partial needs ceil(qlen_host/SCAN_TILE)+1 int64.
+// partial needs ceil(qlen_host/SCAN_TILE)+2 int64; total_out (device, may be
+// NULL) receives the edge total.
 template <typename OffT>
 int launch_td_scan(const Launch& L, const OffT* off, const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host,
-                   int64_t total, int64_t* scan, int32_t* tile_start, int64_t* partial);
+                   int64_t* scan, int32_t* tile_start, int64_t* partial, int64_t* total_out);
 
 template <typename OffT>
 void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t* cols, int64_t nnz,
@@ -64,6 +65,34 @@ void launch_clear_words(const Launch& L, uint64_t* w, int64_t nw);
 void launch_bitmap_to_queue(const Launch& L, const uint64_t* bits, int64_t W, int32_t* q, uint64_t* qlen_ctr);
 void launch_merge(const Launch& L, bool min_mode, uint64_t* visited, uint64_t* vprev, uint64_t* claim,
                   uint64_t* fnext, int64_t W);
+
+// ---- DCSC block ----------------------------------------------------------
+struct BlockArgs {
+    int64_t nrows, ncols, col_base, nzc, nzr, nnz;
+    const int32_t *jc, *ir, *jr, *ic;
+    const int64_t *cp, *rp;
+};
+struct BlockWs {
+    uint64_t* header;   // 8 words cleared per call: [0] qlen, [1] total, [2..4] range
+    uint64_t* qlen;
+    int64_t* total;
+    uint64_t* range;
+    int32_t* q;
+    int64_t* scan;
+    int32_t* tiles;
+    int64_t* partial;
+    uint32_t* spa;      // nrows complemented minimum parents, 0 = empty (kept zero between calls)
+    uint64_t* occ;      // occupied rows (kept zero between calls)
+    int32_t* bpar;
+    uint64_t* bmask;
+};
+void launch_block_td(const Launch& L, const BlockArgs& B, const int32_t* F, int64_t nf, int32_t* out_rows,
+                     int32_t* out_parents, int64_t* nout, const BlockWs& W);
+void launch_block_bu(const Launch& L, const BlockArgs& B, const uint64_t* fbits, uint64_t* completed,
+                     int64_t row_lo, int64_t row_hi, int serial_len, int32_t* out_rows, int32_t* out_parents,
+                     int64_t* nout, const BlockWs& W);
+void launch_validate_dcs(const Launch& L, const int32_t* j, const int64_t* p, const int32_t* minor, int64_t nz,
+                         int64_t nmajor, int64_t nminor, int64_t nnz, bool sorted, uint32_t* err);
 
 template <typename OffT>
 void launch_validate_csr(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, int64_t nnz,

@@ -26,55 +26,9 @@
 //   keeping the first hit in row order (the minimum-id parent).  The wave's
 //   ballot of found lanes is the next-frontier word and updates the visited
 //   word, so the sweep needs no atomics except three counters per workgroup.
-#include "bfs_internal.h"
+#include "bfs_device.h"
 
 namespace bfsk {
-
-__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
-
-__device__ __forceinline__ uint64_t lanemask_lt() {
-    return (1ull << lane_id()) - 1ull;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T x) {
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, WAVE);
-    return x;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_incl_scan(T x) {
-    for (int d = 1; d < WAVE; d <<= 1) {
-        T y = __shfl_up(x, d, WAVE);
-        if (lane_id() >= d) x += y;
-    }
-    return x;
-}
-
-// Sum of (a, b, c) over the workgroup, added once to three counters.
-template <int NWAVES>
-__device__ __forceinline__ void block_add3(uint64_t a, uint64_t b, uint64_t c, uint64_t* ca, uint64_t* cb,
-                                           uint64_t* cc) {
-    __shared__ uint64_t red[3][NWAVES];
-    a = wave_sum(a); b = wave_sum(b); c = wave_sum(c);
-    int wid = threadIdx.x / WAVE;
-    if (lane_id() == 0) { red[0][wid] = a; red[1][wid] = b; red[2][wid] = c; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t x = 0, y = 0, z = 0;
-        for (int i = 0; i < NWAVES; ++i) { x += red[0][i]; y += red[1][i]; z += red[2][i]; }
-        if (x && ca) atomicAdd((unsigned long long*)ca, (unsigned long long)x);
-        if (y && cb) atomicAdd((unsigned long long*)cb, (unsigned long long)y);
-        if (z && cc) atomicAdd((unsigned long long*)cc, (unsigned long long)z);
-    }
-}
-
-static inline int grid_for(int64_t items, int per_block, int cap) {
-    int64_t g = (items + per_block - 1) / per_block;
-    if (g < 1) g = 1;
-    if (g > cap) g = cap;
-    return (int)g;
-}
 
 // ------------------------------------------------------------------ init
 // isolated mask: bit set for vertices without entries and for ids >= n in
@@ -139,127 +93,10 @@ void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, ui
 
 // ------------------------------------------------------------------ frontier degree scan
 template <typename OffT>
-__device__ __forceinline__ int64_t qdeg(const OffT* off, const int32_t* q, int64_t i) {
-    int32_t u = q[i];
-    return (int64_t)off[u + 1] - (int64_t)off[u];
-}
-
-// per-workgroup sums of SCAN_TILE queue entries' degrees
-__device__ __forceinline__ int64_t qlen_of(const uint64_t* qlen_dev, int64_t qlen_host) {
-    return qlen_dev ? (int64_t)*qlen_dev : qlen_host;
-}
-
-template <typename OffT>
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_partials(const OffT* __restrict__ off,
-                                                               const int32_t* __restrict__ q,
-                                                               const uint64_t* __restrict__ qlen_dev,
-                                                               int64_t qlen_host, int64_t* __restrict__ partial) {
-    __shared__ int64_t red[SCAN_BLOCK / WAVE];
-    const int64_t qlen = qlen_of(qlen_dev, qlen_host);
-    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
-    int64_t s = 0;
-    for (int k = 0; k < SCAN_IPT; ++k)
-        if (base + k < qlen) s += qdeg(off, q, base + k);
-    s = wave_sum(s);
-    if (lane_id() == 0) red[threadIdx.x / WAVE] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t t = 0;
-        for (int i = 0; i < SCAN_BLOCK / WAVE; ++i) t += red[i];
-        partial[blockIdx.x] = t;
-    }
-}
-
-// exclusive scan of partial[0..nb) in place, one workgroup
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_top(int64_t* __restrict__ partial, int64_t nb) {
-    __shared__ int64_t wsum[SCAN_BLOCK / WAVE];
-    __shared__ int64_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int64_t c0 = 0; c0 < nb; c0 += SCAN_BLOCK) {
-        int64_t i = c0 + threadIdx.x;
-        int64_t x = i < nb ? partial[i] : 0;
-        int64_t inc = wave_incl_scan(x);
-        int wid = threadIdx.x / WAVE;
-        if (lane_id() == WAVE - 1) wsum[wid] = inc;
-        __syncthreads();
-        if (wid == 0) {
-            int64_t t = lane_id() < SCAN_BLOCK / WAVE ? wsum[lane_id()] : 0;
-            t = wave_incl_scan(t);
-            if (lane_id() < SCAN_BLOCK / WAVE) wsum[lane_id()] = t;
-        }
-        __syncthreads();
-        int64_t before = (wid ? wsum[wid - 1] : 0) + carry;
-        if (i < nb) partial[i] = before + inc - x;
-        __syncthreads();
-        if (threadIdx.x == 0) carry += wsum[SCAN_BLOCK / WAVE - 1];
-        __syncthreads();
-    }
-}
-
-// scan[i] for every queue entry, scan[qlen] = total, and the tile partition:
-// the entry whose edge range [scan[i], scan[i]+deg) holds t*TD_TILE owns tile t.
-template <typename OffT>
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const OffT* __restrict__ off,
-                                                            const int32_t* __restrict__ q,
-                                                            const uint64_t* __restrict__ qlen_dev, int64_t qlen_host,
-                                                            const int64_t* __restrict__ partial, int64_t total,
-                                                            int64_t ntiles, int64_t* __restrict__ scan,
-                                                            int32_t* __restrict__ tile_start) {
-    __shared__ int64_t wsum[SCAN_BLOCK / WAVE];
-    const int64_t qlen = qlen_of(qlen_dev, qlen_host);
-    int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
-    int64_t d[SCAN_IPT];
-    int64_t s = 0;
-    for (int k = 0; k < SCAN_IPT; ++k) {
-        d[k] = (base + k < qlen) ? qdeg(off, q, base + k) : 0;
-        s += d[k];
-    }
-    int64_t inc = wave_incl_scan(s);
-    int wid = threadIdx.x / WAVE;
-    if (lane_id() == WAVE - 1) wsum[wid] = inc;
-    __syncthreads();
-    if (wid == 0) {
-        int64_t t = lane_id() < SCAN_BLOCK / WAVE ? wsum[lane_id()] : 0;
-        t = wave_incl_scan(t);
-        if (lane_id() < SCAN_BLOCK / WAVE) wsum[lane_id()] = t;
-    }
-    __syncthreads();
-    int64_t run = (partial ? partial[blockIdx.x] : 0) + (wid ? wsum[wid - 1] : 0) + inc - s;
-    for (int k = 0; k < SCAN_IPT; ++k) {
-        int64_t i = base + k;
-        if (i >= qlen) break;
-        scan[i] = run;
-        if (d[k] > 0) {
-            int64_t t0 = (run + TD_TILE - 1) / TD_TILE;
-            int64_t t1 = (run + d[k] - 1) / TD_TILE;
-            for (int64_t t = t0; t <= t1; ++t) tile_start[t] = (int32_t)i;
-        }
-        run += d[k];
-    }
-    if (base <= qlen - 1 && qlen - 1 < base + SCAN_IPT) {
-        scan[qlen] = total;
-        tile_start[ntiles] = (int32_t)(qlen - 1);
-    }
-}
-
-template <typename OffT>
 int launch_td_scan(const Launch& L, const OffT* off, const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host,
-                   int64_t total, int64_t* scan, int32_t* tile_start, int64_t* partial) {
-    // qlen_host is exact when qlen_dev is NULL and an upper bound otherwise
-    int64_t nb = (qlen_host + SCAN_TILE - 1) / SCAN_TILE;
-    int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
-    int launches = 1;
-    if (nb > 1) {
-        hipLaunchKernelGGL(k_scan_partials<OffT>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, L.stream, off, q,
-                           qlen_dev, qlen_host, partial);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_BLOCK), 0, L.stream, partial, nb);
-        launches += 2;
-    }
-    hipLaunchKernelGGL(k_scan_apply<OffT>, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(SCAN_BLOCK), 0, L.stream, off,
-                       q, qlen_dev, qlen_host, nb > 1 ? (const int64_t*)partial : nullptr, total, ntiles, scan,
-                       tile_start);
-    return launches;
+                   int64_t* scan, int32_t* tile_start, int64_t* partial, int64_t* total_out) {
+    return launch_scan(L.stream, QueueDegree<OffT>{off, q}, qlen_dev, qlen_host, partial,
+                       TileSink{scan, tile_start, total_out});
 }
 
 // ------------------------------------------------------------------ top-down expand
@@ -267,7 +104,7 @@ template <typename OffT, int MODE>
 __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
     const OffT* __restrict__ off, const int32_t* __restrict__ cols, const int32_t* __restrict__ q,
     const uint64_t* __restrict__ qlen_dev, int64_t qlen_host, const int64_t* __restrict__ scan,
-    const int32_t* __restrict__ tile_start, int64_t total, int64_t ntiles, int64_t nnz,
+    const int32_t* __restrict__ tile_start, const int64_t* __restrict__ total_dev, int64_t total_host, int64_t nnz,
     int32_t* __restrict__ parent, int32_t* __restrict__ depth, uint64_t* __restrict__ visited,
     uint64_t* __restrict__ claim, int32_t* __restrict__ qnext, uint64_t* __restrict__ slot,
     uint64_t* __restrict__ zslot, int32_t next_depth) {
@@ -279,7 +116,9 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
     __shared__ uint64_t s_qbase;
 
     if (blockIdx.x == 0 && threadIdx.x < SLOT_WORDS && zslot) zslot[threadIdx.x] = 0;
-    const int64_t qlen = qlen_of(qlen_dev, qlen_host);
+    const int64_t qlen = len_of(qlen_dev, qlen_host);
+    const int64_t total = total_dev ? *total_dev : total_host;
+    const int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
     uint64_t my_n = 0, my_m = 0;
     const int lane = lane_id();
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -391,12 +230,13 @@ void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t*
                       const int32_t* tile_start, int64_t total, int32_t* parent, int32_t* depth,
                       uint64_t* visited, uint64_t* claim, int32_t* qnext, uint64_t* slot, uint64_t* zslot,
                       int32_t next_depth) {
-    int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
-    int g = grid_for(ntiles, 1, L.grid_cap);
+    const int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
+    const int g = grid_for(ntiles, 1, L.grid_cap);
+    const int64_t* total_dev = nullptr;
 #define BFS_EXPAND(M)                                                                                        \
     hipLaunchKernelGGL((k_td_expand<OffT, M>), dim3(g), dim3(TD_BLOCK), 0, L.stream, off, cols, q, qlen_dev, \
-                       qlen_host, scan, tile_start, total, ntiles, nnz, parent, depth, visited, claim, qnext,  \
-                       slot, zslot, next_depth)
+                       qlen_host, scan, tile_start, total_dev, total, nnz, parent, depth, visited, claim,      \
+                       qnext, slot, zslot, next_depth)
     if (mode == CLAIM_MIN) BFS_EXPAND(CLAIM_MIN);
     else if (mode == CLAIM_CAS) BFS_EXPAND(CLAIM_CAS);
     else BFS_EXPAND(CLAIM_BITMAP);
@@ -628,8 +468,8 @@ void launch_validate_csr(const Launch& L, const OffT* off, const int32_t* cols, 
 // ------------------------------------------------------------------ instantiations
 #define BFS_INST(T)                                                                                              \
     template void launch_isolated_mask<T>(const Launch&, const T*, int64_t, int64_t, uint64_t*, uint64_t*);      \
-    template int launch_td_scan<T>(const Launch&, const T*, const int32_t*, const uint64_t*, int64_t, int64_t,  \
-                                   int64_t*, int32_t*, int64_t*);                                               \
+    template int launch_td_scan<T>(const Launch&, const T*, const int32_t*, const uint64_t*, int64_t, int64_t*, \
+                                   int32_t*, int64_t*, int64_t*);                                               \
     template void launch_td_expand<T>(const Launch&, int, const T*, const int32_t*, int64_t, const int32_t*,   \
                                       const uint64_t*, int64_t, const int64_t*, const int32_t*, int64_t,        \
                                       int32_t*, int32_t*, uint64_t*, uint64_t*, int32_t*, uint64_t*,            \
