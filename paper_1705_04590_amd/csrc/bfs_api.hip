@@ -150,7 +150,31 @@ BlockArgs block_args(const bfs_graph* g) {
     return B;
 }
 
-size_t multi_bytes(const bfs_graph*, int) { return 0; }
+struct MultiLayout {
+    size_t counters, src, visited, F, N, qa, qb, scan, tiles, partial, par, lvl, total;
+};
+
+MultiLayout multi_layout(const bfs_graph* g) {
+    MultiLayout L{};
+    const int64_t n = g->n;
+    size_t o = 0;
+    L.counters = o; o = align_up(o + sizeof(uint64_t) * SLOTS * SLOT_WORDS);
+    L.src = o; o = align_up(o + sizeof(int64_t) * 64);
+    L.visited = o; o = align_up(o + sizeof(uint64_t) * (size_t)n);
+    L.F = o; o = align_up(o + sizeof(uint64_t) * (size_t)n);
+    L.N = o; o = align_up(o + sizeof(uint64_t) * (size_t)n);
+    L.qa = o; o = align_up(o + sizeof(int32_t) * (size_t)(n + 1));
+    L.qb = o; o = align_up(o + sizeof(int32_t) * (size_t)(n + 1));
+    L.scan = o; o = align_up(o + sizeof(int64_t) * (size_t)(n + 2));
+    L.tiles = o; o = align_up(o + sizeof(int32_t) * (size_t)((g->nnz + TD_TILE - 1) / TD_TILE + 2));
+    L.partial = o; o = align_up(o + sizeof(int64_t) * (size_t)((n + SCAN_TILE - 1) / SCAN_TILE + 2));
+    L.par = o; o = align_up(o + sizeof(int32_t) * 64 * (size_t)n);
+    L.lvl = o; o = align_up(o + sizeof(uint16_t) * 64 * (size_t)n);
+    L.total = o;
+    return L;
+}
+
+size_t multi_bytes(const bfs_graph* g, int) { return multi_layout(g).total; }
 
 // -------------------------------------------------------------- timing
 struct Timer {
@@ -343,6 +367,146 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             HIP_TRY(hipStreamSynchronize(stream));
             T.collect(st);
         }
+        st->total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    return BFS_OK;
+}
+
+template <typename OffT>
+bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& o, int32_t* parent, int32_t* depth,
+                     char* ws, hipStream_t stream, bfs_stats* st) {
+    const auto t_start = std::chrono::steady_clock::now();
+    const OffT* off = (const OffT*)g->off;
+    const int64_t n = g->n;
+    const MultiLayout Lo = multi_layout(g);
+    uint64_t* counters = (uint64_t*)(ws + Lo.counters);
+    int64_t* d_src = (int64_t*)(ws + Lo.src);
+    uint64_t* visited = (uint64_t*)(ws + Lo.visited);
+    uint64_t* F = (uint64_t*)(ws + Lo.F);
+    uint64_t* N = (uint64_t*)(ws + Lo.N);
+    int32_t* qa = (int32_t*)(ws + Lo.qa);
+    int32_t* qb = (int32_t*)(ws + Lo.qb);
+    int64_t* scan = (int64_t*)(ws + Lo.scan);
+    int32_t* tiles = (int32_t*)(ws + Lo.tiles);
+    int64_t* partial = (int64_t*)(ws + Lo.partial);
+    int32_t* par_vm = (int32_t*)(ws + Lo.par);
+    uint16_t* lvl_vm = (uint16_t*)(ws + Lo.lvl);
+    const uint64_t full = k == 64 ? ~0ull : ((1ull << k) - 1);
+    const int serial = o.bu_serial > 0 ? o.bu_serial : 16;
+    Launch L{stream, o.grid_blocks > 0 ? o.grid_blocks : 2048};
+    Timer T{g, stream, o.timing != 0, {}, 0};
+    uint64_t* h = g->h_buf;
+
+    // sources travel through the pinned buffer (k <= 64 ids)
+    std::memcpy(h, h_src, sizeof(int64_t) * (size_t)k);
+    HIP_TRY(hipMemcpyAsync(d_src, h, sizeof(int64_t) * (size_t)k, hipMemcpyHostToDevice, stream));
+    uint64_t* slot_init = counters + (size_t)(SLOTS - 1) * SLOT_WORDS;   // "level -1"
+    HIP_TRY(T.begin());
+    launch_ms_init<OffT>(L, off, n, k, d_src, g->d_iso, visited, F, N, par_vm, lvl_vm, qa, counters, slot_init);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(T.end(BFS_K_INIT, -1));
+    HIP_TRY(hipMemcpyAsync(h, slot_init, sizeof(uint64_t) * SLOT_WORDS, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (st) st->launches[BFS_K_INIT] += 2;
+
+    int64_t n_f = (int64_t)h[M_SLOT_NNEXT], m_f = (int64_t)h[M_SLOT_MNEXT];
+    int64_t qlen = (int64_t)h[M_SLOT_QLEN];   // frontier vertices with edges (all of them after level 0)
+    int64_t m_u = g->nnz - (k == 1 ? m_f : 0);
+    int cur_dir = (o.dir == BFS_DIR_BU) ? 1 : 0;
+    bool fq_valid = true;          // qa lists the vertices with F != 0 (n_f of them)
+    int n_dirty = 0;               // N: 0 clean, 1 dirty at the qb list (nd_len), 2 dirty anywhere
+    int64_t nd_len = 0;
+    int level = 0;
+    int64_t examined = 0, reached_pairs = 0;
+    for (;;) {
+        if (level >= 65535) return fail(BFS_E_UNSUPPORTED, "more than 65535 levels");
+        if (o.dir == BFS_DIR_TD) cur_dir = 0;
+        else if (o.dir == BFS_DIR_BU) cur_dir = 1;
+        else if (cur_dir == 0) { if ((double)m_f * o.alpha > (double)m_u) cur_dir = 1; }
+        else { if ((double)n_f * o.beta < (double)n) cur_dir = 0; }
+        uint64_t* slot = counters + (size_t)(level % SLOTS) * SLOT_WORDS;
+        uint64_t* zslot = counters + (size_t)((level + 1) % SLOTS) * SLOT_WORDS;
+        uint64_t* pslot = counters + (size_t)((level + SLOTS - 1) % SLOTS) * SLOT_WORDS;
+        const uint16_t next_level = (uint16_t)(level + 1);
+        if (cur_dir == 0) {
+            HIP_TRY(T.begin());
+            int conv = 0;
+            if (!fq_valid) {
+                launch_ms_mask_to_queue(L, F, n, qa, slot + M_SLOT_CONV);
+                fq_valid = true;
+                qlen = n_f;
+                ++conv;
+            }
+            if (n_dirty == 2) { launch_clear_words(L, N, n); ++conv; }
+            else if (n_dirty == 1 && nd_len > 0) { launch_ms_clear_queue(L, qb, nullptr, nd_len, N); ++conv; }
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(T.end(BFS_K_CONVERT, level));
+            HIP_TRY(T.begin());
+            if (m_f > 0)
+                launch_ms_td<OffT>(L, off, g->cols, g->nnz, qa, qlen, m_f, scan, tiles, partial, F, N, visited, full,
+                                   qb, par_vm, lvl_vm, next_level, serial, slot, zslot);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(T.end(BFS_K_MS_LEVEL, level));
+            if (st) { st->launches[BFS_K_CONVERT] += conv; st->launches[BFS_K_MS_LEVEL] += m_f > 0 ? 3 : 0; }
+        } else {
+            HIP_TRY(T.begin());
+            launch_ms_bu<OffT>(L, off, g->cols, n, F, N, visited, full, pslot + M_SLOT_OR, par_vm, lvl_vm,
+                               next_level, serial, slot, zslot);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(T.end(BFS_K_MS_LEVEL, level));
+            if (st) st->launches[BFS_K_MS_LEVEL] += 1;
+        }
+        HIP_TRY(hipMemcpyAsync(h, slot, sizeof(uint64_t) * SLOT_WORDS, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        const int64_t n_next = (int64_t)h[M_SLOT_NNEXT], m_next = (int64_t)h[M_SLOT_MNEXT];
+        const int64_t lvl_exam = cur_dir == 0 ? m_f + (int64_t)h[M_SLOT_EXAM] : (int64_t)h[M_SLOT_EXAM];
+        examined += lvl_exam;
+        if (st && level < BFS_STATS_MAX_LEVELS) {
+            st->level_dir[level] = (int8_t)cur_dir;
+            st->level_nf[level] = n_f;
+            st->level_mf[level] = m_f;
+            st->level_mu[level] = m_u;
+            st->level_unvisited[level] = -1;
+            st->level_examined[level] = lvl_exam;
+        }
+        if (st) { if (cur_dir == 0) st->td_levels++; else st->bu_levels++; }
+        // frontier <- next; the old frontier array becomes the next buffer
+        uint64_t* t = F; F = N; N = t;
+        if (cur_dir == 0) {
+            int32_t* tq = qa; qa = qb; qb = tq;   // qa: new frontier list, qb: dirty list of N
+            n_dirty = 1;
+            nd_len = qlen;
+            qlen = n_next;
+            fq_valid = true;
+        } else {
+            if (fq_valid) {
+                int32_t* tq = qa; qa = qb; qb = tq;
+                n_dirty = 1;
+                nd_len = qlen;
+            } else {
+                n_dirty = 2;
+            }
+            fq_valid = false;
+        }
+        ++level;
+        if (n_next == 0) break;
+        reached_pairs += n_next;
+        m_u -= (int64_t)h[M_SLOT_MFULL];
+        n_f = n_next;
+        m_f = m_next;
+    }
+    HIP_TRY(T.begin());
+    launch_ms_output(L, n, k, d_src, visited, g->d_iso, par_vm, lvl_vm, parent, depth);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(T.end(BFS_K_MS_OUTPUT, -1));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (st) {
+        st->launches[BFS_K_MS_OUTPUT] += 1;
+        st->levels = level;
+        st->reached = reached_pairs;
+        st->isolated = g->isolated;
+        st->edges_examined = examined;
+        if (T.on) T.collect(st);
         st->total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     }
     return BFS_OK;
@@ -587,9 +751,37 @@ bfs_status bfs_run(bfs_graph* g, int64_t source, const bfs_opts* opts, int32_t* 
 bfs_status bfs_run_multi(bfs_graph* g, const int64_t* h_sources, int k, const bfs_opts* opts, int32_t* d_parent,
                          int32_t* d_depth, void* d_workspace, size_t workspace_bytes, void* hip_stream,
                          bfs_stats* stats) {
-    (void)g; (void)h_sources; (void)k; (void)opts; (void)d_parent; (void)d_depth; (void)d_workspace;
-    (void)workspace_bytes; (void)hip_stream; (void)stats;
-    return fail(BFS_E_UNSUPPORTED, "bfs_run_multi is not built yet");
+    bfs_status s = check_csr_graph(g);
+    if (s != BFS_OK) return s;
+    bfs_opts o;
+    bfs_opts_default(&o);
+    if (opts) o = *opts;
+    if (k < 1 || k > 64) return fail(BFS_E_INVALID_ARG, "k=%d outside [1, 64]", k);
+    if (!h_sources) return fail(BFS_E_INVALID_ARG, "sources is NULL");
+    for (int j = 0; j < k; ++j)
+        if (h_sources[j] < 0 || h_sources[j] >= g->n)
+            return fail(BFS_E_OUT_OF_RANGE, "source %d = %lld outside [0, %lld)", j, (long long)h_sources[j],
+                        (long long)g->n);
+    if (o.dir < BFS_DIR_DO || o.dir > BFS_DIR_BU) return fail(BFS_E_INVALID_ARG, "bad dir %d", o.dir);
+    if (!(o.alpha > 0) || !(o.beta > 0)) return fail(BFS_E_INVALID_ARG, "alpha and beta must be > 0");
+    if (!d_depth || !d_workspace) return fail(BFS_E_INVALID_ARG, "NULL depth output or workspace");
+    if ((uintptr_t)d_workspace % ALIGN) return fail(BFS_E_INVALID_ARG, "workspace not 256-byte aligned");
+    if (!(g->flags & BFS_GRAPH_SYMMETRIC) || !(g->flags & BFS_GRAPH_SORTED))
+        return fail(BFS_E_UNSUPPORTED, "multi-source search needs a SYMMETRIC and SORTED graph");
+    const size_t need = multi_layout(g).total;
+    if (workspace_bytes < need) return fail(BFS_E_BUDGET, "workspace %zu < %zu bytes", workspace_bytes, need);
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev != g->device) {
+        if (hipSetDevice(g->device) != hipSuccess) return fail(BFS_E_HIP, "hipSetDevice(%d) failed", g->device);
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (g->off_bytes == 4)
+        s = run_multi<int32_t>(g, h_sources, k, o, d_parent, d_depth, (char*)d_workspace, st, stats);
+    else
+        s = run_multi<int64_t>(g, h_sources, k, o, d_parent, d_depth, (char*)d_workspace, st, stats);
+    if (dev != g->device) (void)hipSetDevice(dev);
+    return s;
 }
 
 bfs_status bfs_block_td(bfs_graph* g, const int32_t* d_frontier, int64_t nf, int32_t* d_out_rows,

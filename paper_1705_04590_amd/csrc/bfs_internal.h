@@ -66,6 +66,30 @@ void launch_bitmap_to_queue(const Launch& L, const uint64_t* bits, int64_t W, in
 void launch_merge(const Launch& L, bool min_mode, uint64_t* visited, uint64_t* vprev, uint64_t* claim,
                   uint64_t* fnext, int64_t W);
 
+// ---- multi-source --------------------------------------------------------
+enum { M_SLOT_QLEN = 0, M_SLOT_NNEXT = 1, M_SLOT_MNEXT = 2, M_SLOT_OR = 3, M_SLOT_MFULL = 4, M_SLOT_EXAM = 5,
+       M_SLOT_CONV = 6 };
+
+template <typename OffT>
+void launch_ms_init(const Launch& L, const OffT* off, int64_t n, int k, const int64_t* src, const uint64_t* iso,
+                    uint64_t* visited, uint64_t* F, uint64_t* N, int32_t* par_vm, uint16_t* lvl_vm, int32_t* q,
+                    uint64_t* counters, uint64_t* slot0);
+template <typename OffT>
+void launch_ms_td(const Launch& L, const OffT* off, const int32_t* cols, int64_t nnz, const int32_t* q, int64_t qlen,
+                  int64_t total, int64_t* scan, int32_t* tiles, int64_t* partial, const uint64_t* F, uint64_t* N,
+                  uint64_t* visited, uint64_t full, int32_t* qnext, int32_t* par_vm, uint16_t* lvl_vm,
+                  uint16_t level, int serial, uint64_t* slot, uint64_t* zslot);
+template <typename OffT>
+void launch_ms_bu(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, const uint64_t* F, uint64_t* N,
+                  uint64_t* visited, uint64_t full, const uint64_t* active_dev, int32_t* par_vm, uint16_t* lvl_vm,
+                  uint16_t level, int serial, uint64_t* slot, uint64_t* zslot);
+void launch_ms_mask_to_queue(const Launch& L, const uint64_t* N, int64_t n, int32_t* q, uint64_t* qlen);
+void launch_ms_clear_queue(const Launch& L, const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host,
+                           uint64_t* M);
+void launch_ms_output(const Launch& L, int64_t n, int k, const int64_t* src, const uint64_t* visited,
+                      const uint64_t* iso, const int32_t* par_vm, const uint16_t* lvl_vm, int32_t* parent,
+                      int32_t* depth);
+
 // ---- DCSC block ----------------------------------------------------------
 struct BlockArgs {
     int64_t nrows, ncols, col_base, nzc, nzr, nnz;

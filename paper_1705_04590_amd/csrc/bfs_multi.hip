@@ -1,0 +1,497 @@
+// Multi-source BFS: up to 64 searches at once, one bit per source in
+// per-vertex uint64 masks (visited, frontier F, next N), gfx950.
+//
+// A top-down level expands the queue of vertices whose frontier mask is not
+// zero over the same edge-balanced tiles as the single-source step; an edge
+// (u, v) ORs F[u] & ~visited[v] into N[v] with one 64-bit atomic, and the
+// thread that turns N[v] from zero to non-zero queues v.  A resolve pass then
+// gives every queued v its parents: it scans v's sorted row and, for each
+// bit of N[v], keeps the first neighbour whose frontier mask carries it
+// (the minimum-id parent of that source).  A bottom-up level instead sweeps
+// every vertex with bits still missing, ORing the frontier masks of its
+// sorted neighbours and recording the first supplier of each new bit, until
+// all missing bits of currently active sources are found.  Long rows are
+// scanned by the whole wave with an exclusive prefix-OR across lanes, which
+// names the first supplying lane of every bit.
+//
+// Results are written per (vertex, source) into a vertex-major scratch
+// ([n][64] parents, [n][64] 16-bit levels) exactly once, and a final pass
+// transposes them into the caller's source-major parent/depth arrays,
+// writing -1 where the visited mask says a source never reached a vertex.
+#include "bfs_device.h"
+
+namespace bfsk {
+
+// counter slot words of a multi-source level
+enum { M_QLEN = 0, M_NNEXT = 1, M_MNEXT = 2, M_OR = 3, M_MFULL = 4, M_EXAM = 5 };
+
+__device__ __forceinline__ void or_reduce_add(uint64_t n, uint64_t m, uint64_t orv, uint64_t mfull, uint64_t exam,
+                                              uint64_t* slot) {
+    __shared__ uint64_t red[5][4];
+    n = wave_sum(n); m = wave_sum(m); mfull = wave_sum(mfull); exam = wave_sum(exam);
+    for (int d = 32; d >= 1; d >>= 1) orv |= __shfl_xor(orv, d, WAVE);
+    const int wid = threadIdx.x / WAVE;
+    if (lane_id() == 0) { red[0][wid] = n; red[1][wid] = m; red[2][wid] = orv; red[3][wid] = mfull; red[4][wid] = exam; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t a = 0, b = 0, c = 0, e = 0, x = 0;
+        for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) {
+            a += red[0][i]; b += red[1][i]; c |= red[2][i]; e += red[3][i]; x += red[4][i];
+        }
+        if (a) atomicAdd((unsigned long long*)&slot[M_NNEXT], (unsigned long long)a);
+        if (b) atomicAdd((unsigned long long*)&slot[M_MNEXT], (unsigned long long)b);
+        if (c) atomicOr((unsigned long long*)&slot[M_OR], (unsigned long long)c);
+        if (e) atomicAdd((unsigned long long*)&slot[M_MFULL], (unsigned long long)e);
+        if (x) atomicAdd((unsigned long long*)&slot[M_EXAM], (unsigned long long)x);
+    }
+}
+
+__device__ __forceinline__ void record(int32_t* __restrict__ par_vm, uint16_t* __restrict__ lvl_vm, int64_t v,
+                                       uint64_t bits, int32_t u, uint16_t level) {
+    while (bits) {
+        const int j = __ffsll((unsigned long long)bits) - 1;
+        bits &= bits - 1;
+        par_vm[v * 64 + j] = u;
+        lvl_vm[v * 64 + j] = level;
+    }
+}
+
+// ---------------------------------------------------------------- init
+template <typename OffT>
+__global__ void k_ms_init(int64_t n, uint64_t full, const uint64_t* __restrict__ iso, uint64_t* __restrict__ visited,
+                          uint64_t* __restrict__ F, uint64_t* __restrict__ N, uint64_t* __restrict__ counters) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        // vertices without edges are reached by no search but their own
+        const bool empty = iso && ((iso[v >> 6] >> (v & 63)) & 1ull);
+        visited[v] = empty ? full : 0ull;
+        F[v] = 0;
+        N[v] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < SLOTS * SLOT_WORDS) counters[threadIdx.x] = 0;
+}
+
+// one workgroup of 64 threads: thread j seeds source j, the first thread of
+// every distinct source vertex queues it, and the level-0 counters are set
+template <typename OffT>
+__global__ void k_ms_sources(const OffT* __restrict__ off, const int64_t* __restrict__ src, int k,
+                             uint64_t* __restrict__ visited, uint64_t* __restrict__ F, int32_t* __restrict__ par_vm,
+                             uint16_t* __restrict__ lvl_vm, int32_t* __restrict__ q, uint64_t* __restrict__ slot) {
+    const int j = threadIdx.x;
+    int64_t s = -1;
+    bool first = false;
+    if (j < k) {
+        s = src[j];
+        first = true;
+        for (int i = 0; i < j; ++i)
+            if (src[i] == s) first = false;
+        par_vm[s * 64 + j] = (int32_t)s;
+        lvl_vm[s * 64 + j] = 0;
+    }
+    // all bits of one vertex are set by its first thread (no atomics needed);
+    // a source without edges is visited by its own search and expands nothing
+    uint64_t bits = 0;
+    int64_t d = 0;
+    if (first) {
+        for (int i = j; i < k; ++i)
+            if (src[i] == s) bits |= 1ull << i;
+        d = (int64_t)off[s + 1] - (int64_t)off[s];
+        visited[s] |= bits;
+        if (d > 0) F[s] = bits;
+    }
+    const uint64_t m = __ballot(first);
+    const uint64_t mq = __ballot(first && d > 0);
+    if (first && d > 0) {
+        q[__popcll(mq & lanemask_lt())] = (int32_t)s;
+        atomicAdd((unsigned long long*)&slot[M_MNEXT], (unsigned long long)d);
+    }
+    if (j == 0) {
+        slot[M_QLEN] = (uint64_t)__popcll(mq);
+        slot[M_NNEXT] = (uint64_t)__popcll(m);
+        slot[M_OR] = k == 64 ? ~0ull : ((1ull << k) - 1);
+    }
+}
+
+// ---------------------------------------------------------------- top-down
+template <typename OffT>
+__global__ __launch_bounds__(TD_BLOCK) void k_ms_td_expand(
+    const OffT* __restrict__ off, const int32_t* __restrict__ cols, const int32_t* __restrict__ q,
+    int64_t qlen, const int64_t* __restrict__ scan, const int32_t* __restrict__ tile_start,
+    int64_t total, int64_t nnz, const uint64_t* __restrict__ F, const uint64_t* __restrict__ visited,
+    uint64_t* __restrict__ N, int32_t* __restrict__ qnext, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot) {
+    __shared__ int32_t s_start[TD_TILE + 1];
+    __shared__ int64_t s_base[TD_TILE + 1];
+    __shared__ uint64_t s_f[TD_TILE + 1];
+    __shared__ int32_t s_out[TD_TILE];
+    __shared__ int s_cnt;
+    __shared__ uint64_t s_qbase;
+    if (blockIdx.x == 0 && threadIdx.x < SLOT_WORDS && zslot) zslot[threadIdx.x] = 0;
+    const int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
+    const int lane = lane_id();
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t e0 = t * TD_TILE;
+        const int64_t e1 = (e0 + TD_TILE < total) ? e0 + TD_TILE : total;
+        const int i0 = tile_start[t];
+        int nv = tile_start[t + 1] - i0 + 1;
+        if (nv > TD_TILE + 1) nv = TD_TILE + 1;
+        if (i0 < 0 || i0 >= qlen) nv = 0;
+        else if (nv > qlen - i0) nv = (int)(qlen - i0);
+        for (int j = threadIdx.x; j < nv; j += TD_BLOCK) {
+            const int32_t u = q[i0 + j];
+            const int64_t sc = scan[i0 + j];
+            const int64_t rel = sc - e0;
+            s_start[j] = rel < 0 ? 0 : (int32_t)rel;
+            s_base[j] = (int64_t)off[u] - sc;
+            s_f[j] = F[u];
+        }
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        int32_t vv[TD_EPT];
+        uint64_t ff[TD_EPT];
+#pragma unroll
+        for (int k = 0; k < TD_EPT; ++k) {
+            const int p = k * TD_BLOCK + threadIdx.x;
+            const int64_t e = e0 + p;
+            vv[k] = -1;
+            ff[k] = 0;
+            if (e < e1 && nv > 0) {
+                int lo = 0, hi = nv - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_start[mid] <= p) lo = mid; else hi = mid - 1;
+                }
+                int64_t pos = s_base[lo] + e;
+                if (pos < 0 || pos >= nnz) pos = 0;
+                vv[k] = cols[pos];
+                ff[k] = s_f[lo];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < TD_EPT; ++k) {
+            bool push = false;
+            if (vv[k] >= 0) {
+                const uint64_t x = ff[k] & ~visited[vv[k]];
+                if (x) {
+                    const uint64_t old = atomicOr((unsigned long long*)&N[vv[k]], (unsigned long long)x);
+                    push = old == 0;
+                }
+            }
+            const uint64_t wm = __ballot(push);
+            if (wm) {
+                const int leader = __ffsll((unsigned long long)wm) - 1;
+                int b = 0;
+                if (lane == leader) b = atomicAdd(&s_cnt, __popcll(wm));
+                b = __shfl(b, leader, WAVE);
+                if (push) s_out[b + __popcll(wm & lanemask_lt())] = vv[k];
+            }
+        }
+        __syncthreads();
+        const int cnt = s_cnt;
+        if (threadIdx.x == 0 && cnt > 0)
+            s_qbase = atomicAdd((unsigned long long*)&slot[M_QLEN], (unsigned long long)cnt);
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt; j += TD_BLOCK) qnext[s_qbase + j] = s_out[j];
+        __syncthreads();
+    }
+}
+
+// Scan the sorted row [beg, end) of v for the first supplier of every bit of
+// `need` among frontier masks F; serial per lane for `serial` entries, then the
+// whole wave on the rows still open.  Returns the bits found; *examined gets
+// the entries looked at up to the last needed supplier (or the row length).
+// Must be called by all lanes of the wave.
+__device__ __forceinline__ uint64_t first_suppliers(const int32_t* __restrict__ cols, const uint64_t* __restrict__ F,
+                                                    int64_t v, int64_t beg, int64_t end, uint64_t need, int serial,
+                                                    int32_t* __restrict__ par_vm, uint16_t* __restrict__ lvl_vm,
+                                                    uint16_t level, int64_t* examined) {
+    const int lane = lane_id();
+    uint64_t found = 0;
+    int64_t p = beg;
+    const int64_t lim = (end - beg > serial) ? beg + serial : end;
+    while (need && p < lim) {
+        const int32_t u = cols[p];
+        const uint64_t x = F[u] & need;
+        if (x) {
+            record(par_vm, lvl_vm, v, x, u, level);
+            found |= x;
+            need &= ~x;
+        }
+        ++p;
+    }
+    int64_t ex = p - beg;
+    uint64_t rem = __ballot(need != 0 && p < end);
+    while (rem) {
+        const int l = __ffsll((unsigned long long)rem) - 1;
+        rem &= rem - 1;
+        const int64_t vl = __shfl(v, l, WAVE);
+        const int64_t pb = __shfl(p, l, WAVE);
+        const int64_t pe = __shfl(end, l, WAVE);
+        uint64_t nd = __shfl(need, l, WAVE);
+        uint64_t got = 0;
+        int64_t last = pb;
+        for (int64_t b = pb; b < pe && nd; b += WAVE) {
+            const int64_t idx = b + lane;
+            int32_t u = 0;
+            uint64_t f = 0;
+            if (idx < pe) {
+                u = cols[idx];
+                f = F[u] & nd;
+            }
+            // exclusive prefix-OR: bits already supplied by lower lanes
+            uint64_t incl = f;
+            for (int d = 1; d < WAVE; d <<= 1) {
+                const uint64_t y = __shfl_up(incl, d, WAVE);
+                if (lane >= d) incl |= y;
+            }
+            uint64_t excl = __shfl_up(incl, 1, WAVE);
+            if (lane == 0) excl = 0;
+            const uint64_t mine = f & ~excl;
+            if (mine) record(par_vm, lvl_vm, vl, mine, u, level);
+            const uint64_t all = __shfl(incl, WAVE - 1, WAVE);
+            // the chunk position where the last needed bit arrived
+            const uint64_t hit = __ballot(mine != 0);
+            if (all) last = b + (63 - __clzll((long long)hit)) + 1;
+            got |= all;
+            nd &= ~all;
+            if (!nd) break;
+            last = (b + WAVE < pe) ? b + WAVE : pe;
+        }
+        if (lane == l) {
+            found |= got;
+            need = nd;
+            ex = (nd ? (pe - pb) : (last - pb)) + (pb - beg);
+        }
+    }
+    *examined = ex;
+    return found;
+}
+
+template <typename OffT>
+__global__ __launch_bounds__(256) void k_ms_resolve(const OffT* __restrict__ off, const int32_t* __restrict__ cols,
+                                                    const int32_t* __restrict__ q, const uint64_t* __restrict__ qlen_dev,
+                                                    const uint64_t* __restrict__ F, uint64_t* __restrict__ N,
+                                                    uint64_t* __restrict__ visited, uint64_t full,
+                                                    int32_t* __restrict__ par_vm, uint16_t* __restrict__ lvl_vm,
+                                                    uint16_t level, int serial, uint64_t* __restrict__ slot) {
+    const int64_t qlen = (int64_t)*qlen_dev;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint64_t cn = 0, cm = 0, cor = 0, cfull = 0, cx = 0;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < qlen; i0 += stride) {
+        const int64_t i = i0 + threadIdx.x;
+        int64_t v = 0, beg = 0, end = 0;
+        uint64_t need = 0;
+        if (i < qlen) {
+            v = q[i];
+            need = N[v];
+            beg = (int64_t)off[v];
+            end = (int64_t)off[v + 1];
+        }
+        int64_t ex = 0;
+        first_suppliers(cols, F, v, beg, end, need, serial, par_vm, lvl_vm, level, &ex);
+        if (i < qlen) {
+            const uint64_t vis = visited[v] | need;
+            visited[v] = vis;
+            cn += 1;
+            cm += (uint64_t)(end - beg);
+            cor |= need;
+            cx += (uint64_t)ex;
+            if (vis == full) cfull += (uint64_t)(end - beg);
+        }
+    }
+    or_reduce_add(cn, cm, cor, cfull, cx, slot);
+}
+
+// ---------------------------------------------------------------- bottom-up
+template <typename OffT>
+__global__ __launch_bounds__(256) void k_ms_bu_sweep(const OffT* __restrict__ off, const int32_t* __restrict__ cols,
+                                                     int64_t n, const uint64_t* __restrict__ F,
+                                                     uint64_t* __restrict__ N, uint64_t* __restrict__ visited,
+                                                     uint64_t full, const uint64_t* __restrict__ active_dev,
+                                                     int32_t* __restrict__ par_vm, uint16_t* __restrict__ lvl_vm,
+                                                     uint16_t level, int serial, uint64_t* __restrict__ slot,
+                                                     uint64_t* __restrict__ zslot) {
+    if (blockIdx.x == 0 && threadIdx.x < SLOT_WORDS && zslot) zslot[threadIdx.x] = 0;
+    const uint64_t active = *active_dev;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint64_t cn = 0, cm = 0, cor = 0, cfull = 0, cx = 0;
+    for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n; v0 += stride) {
+        const int64_t v = v0 + threadIdx.x;
+        uint64_t vis = 0, need = 0;
+        int64_t beg = 0, end = 0;
+        if (v < n) {
+            vis = visited[v];
+            need = ~vis & active;
+            if (need) {
+                beg = (int64_t)off[v];
+                end = (int64_t)off[v + 1];
+            }
+        }
+        int64_t ex = 0;
+        const uint64_t found = first_suppliers(cols, F, v, beg, end, need, serial, par_vm, lvl_vm, level, &ex);
+        if (v < n) {
+            N[v] = found;
+            cx += need ? (uint64_t)ex : 0;
+            if (found) {
+                const uint64_t nv = vis | found;
+                visited[v] = nv;
+                cn += 1;
+                cm += (uint64_t)(end - beg);
+                cor |= found;
+                if (nv == full) cfull += (uint64_t)(end - beg);
+            }
+        }
+    }
+    or_reduce_add(cn, cm, cor, cfull, cx, slot);
+}
+
+// vertices with a non-zero mask -> queue (bottom-up -> top-down)
+__global__ __launch_bounds__(256) void k_ms_mask_to_queue(const uint64_t* __restrict__ N, int64_t n,
+                                                          int32_t* __restrict__ q, uint64_t* __restrict__ qlen) {
+    const int lane = lane_id();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n; v0 += stride) {
+        const int64_t v = v0 + threadIdx.x;
+        const bool on = v < n && N[v] != 0;
+        const uint64_t m = __ballot(on);
+        if (m) {
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            uint64_t b = 0;
+            if (lane == leader) b = atomicAdd((unsigned long long*)qlen, (unsigned long long)__popcll(m));
+            b = __shfl(b, leader, WAVE);
+            if (on) q[b + __popcll(m & lanemask_lt())] = (int32_t)v;
+        }
+    }
+}
+
+// zero the masks of the vertices in a queue (top-down levels keep N sparse)
+__global__ void k_ms_clear_queue(const int32_t* __restrict__ q, const uint64_t* __restrict__ qlen_dev,
+                                 int64_t qlen_host, uint64_t* __restrict__ M) {
+    const int64_t qlen = len_of(qlen_dev, qlen_host);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < qlen; i += stride) M[q[i]] = 0;
+}
+
+// ---------------------------------------------------------------- output
+// transpose a tile of 64 vertices x 64 sources from the vertex-major scratch
+// into source-major outputs; -1 where the source never reached the vertex
+__global__ __launch_bounds__(256) void k_ms_output(int64_t n, int k, const int64_t* __restrict__ src,
+                                                   const uint64_t* __restrict__ visited,
+                                                   const uint64_t* __restrict__ iso,
+                                                   const int32_t* __restrict__ par_vm,
+                                                   const uint16_t* __restrict__ lvl_vm, int32_t* __restrict__ parent,
+                                                   int32_t* __restrict__ depth) {
+    __shared__ int32_t s_p[64][65];
+    __shared__ int32_t s_d[64][65];
+    __shared__ uint64_t s_vis[64];
+    __shared__ int64_t s_src[64];
+    if (threadIdx.x < 64) s_src[threadIdx.x] = threadIdx.x < k ? src[threadIdx.x] : -1;
+    const int64_t ntiles = (n + 63) / 64;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t v0 = t * 64;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int64_t v = v0 + threadIdx.x;
+            uint64_t vis = 0;
+            if (v < n) {
+                vis = visited[v];
+                // vertices without edges were pre-marked visited; only their own search reaches them
+                if (iso && ((iso[v >> 6] >> (v & 63)) & 1ull)) {
+                    vis = 0;
+                    for (int j = 0; j < k; ++j)
+                        if (s_src[j] == v) vis |= 1ull << j;
+                }
+            }
+            s_vis[threadIdx.x] = vis;
+        }
+        __syncthreads();
+        // read: 64 vertices x 64 entries, consecutive threads on consecutive sources
+        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+            const int vi = e >> 6, j = e & 63;
+            const int64_t v = v0 + vi;
+            int32_t pv = -1, dv = -1;
+            if (v < n && j < k && ((s_vis[vi] >> j) & 1ull)) {
+                pv = par_vm[v * 64 + j];
+                dv = lvl_vm[v * 64 + j];
+            }
+            s_p[vi][j] = pv;
+            s_d[vi][j] = dv;
+        }
+        __syncthreads();
+        // write: for each source, 64 consecutive vertices
+        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+            const int j = e >> 6, vi = e & 63;
+            const int64_t v = v0 + vi;
+            if (v < n && j < k) {
+                if (parent) parent[(int64_t)j * n + v] = s_p[vi][j];
+                depth[(int64_t)j * n + v] = s_d[vi][j];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename OffT>
+void launch_ms_init(const Launch& L, const OffT* off, int64_t n, int k, const int64_t* src, const uint64_t* iso,
+                    uint64_t* visited, uint64_t* F, uint64_t* N, int32_t* par_vm, uint16_t* lvl_vm, int32_t* q,
+                    uint64_t* counters, uint64_t* slot0) {
+    const uint64_t full = k == 64 ? ~0ull : ((1ull << k) - 1);
+    hipLaunchKernelGGL(k_ms_init<OffT>, dim3(grid_for(n, 256, L.grid_cap * 4)), dim3(256), 0, L.stream, n, full,
+                       iso, visited, F, N, counters);
+    hipLaunchKernelGGL(k_ms_sources<OffT>, dim3(1), dim3(64), 0, L.stream, off, src, k, visited, F, par_vm, lvl_vm,
+                       q, slot0);
+}
+
+template <typename OffT>
+void launch_ms_td(const Launch& L, const OffT* off, const int32_t* cols, int64_t nnz, const int32_t* q, int64_t qlen,
+                  int64_t total, int64_t* scan, int32_t* tiles, int64_t* partial, const uint64_t* F, uint64_t* N,
+                  uint64_t* visited, uint64_t full, int32_t* qnext, int32_t* par_vm, uint16_t* lvl_vm,
+                  uint16_t level, int serial, uint64_t* slot, uint64_t* zslot) {
+    launch_scan(L.stream, QueueDegree<OffT>{off, q}, (const uint64_t*)nullptr, qlen, partial,
+                TileSink{scan, tiles, nullptr});
+    const int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
+    hipLaunchKernelGGL(k_ms_td_expand<OffT>, dim3(grid_for(ntiles, 1, L.grid_cap)), dim3(TD_BLOCK), 0, L.stream,
+                       off, cols, q, qlen, scan, tiles, total, nnz, F, visited, N, qnext, slot, zslot);
+    // the next queue's length is in slot[M_QLEN], written by the expand
+    hipLaunchKernelGGL(k_ms_resolve<OffT>, dim3(L.grid_cap), dim3(256), 0, L.stream, off, cols, qnext,
+                       (const uint64_t*)&slot[M_QLEN], F, N, visited, full, par_vm, lvl_vm, level, serial, slot);
+}
+
+template <typename OffT>
+void launch_ms_bu(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, const uint64_t* F, uint64_t* N,
+                  uint64_t* visited, uint64_t full, const uint64_t* active_dev, int32_t* par_vm, uint16_t* lvl_vm,
+                  uint16_t level, int serial, uint64_t* slot, uint64_t* zslot) {
+    hipLaunchKernelGGL(k_ms_bu_sweep<OffT>, dim3(grid_for(n, 256, L.grid_cap)), dim3(256), 0, L.stream, off, cols, n,
+                       F, N, visited, full, active_dev, par_vm, lvl_vm, level, serial, slot, zslot);
+}
+
+void launch_ms_mask_to_queue(const Launch& L, const uint64_t* N, int64_t n, int32_t* q, uint64_t* qlen) {
+    hipLaunchKernelGGL(k_ms_mask_to_queue, dim3(grid_for(n, 256, L.grid_cap)), dim3(256), 0, L.stream, N, n, q, qlen);
+}
+
+void launch_ms_clear_queue(const Launch& L, const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host,
+                           uint64_t* M) {
+    hipLaunchKernelGGL(k_ms_clear_queue, dim3(grid_for(qlen_host, 256, L.grid_cap * 4)), dim3(256), 0, L.stream, q,
+                       qlen_dev, qlen_host, M);
+}
+
+void launch_ms_output(const Launch& L, int64_t n, int k, const int64_t* src, const uint64_t* visited,
+                      const uint64_t* iso, const int32_t* par_vm, const uint16_t* lvl_vm, int32_t* parent,
+                      int32_t* depth) {
+    hipLaunchKernelGGL(k_ms_output, dim3(grid_for((n + 63) / 64, 1, L.grid_cap * 2)), dim3(256), 0, L.stream, n, k,
+                       src, visited, iso, par_vm, lvl_vm, parent, depth);
+}
+
+#define MS_INST(T)                                                                                                  \
+    template void launch_ms_init<T>(const Launch&, const T*, int64_t, int, const int64_t*, const uint64_t*,        \
+                                    uint64_t*, uint64_t*, uint64_t*, int32_t*, uint16_t*, int32_t*, uint64_t*,      \
+                                    uint64_t*);                                                                    \
+    template void launch_ms_td<T>(const Launch&, const T*, const int32_t*, int64_t, const int32_t*, int64_t,       \
+                                  int64_t, int64_t*, int32_t*, int64_t*, const uint64_t*, uint64_t*, uint64_t*,    \
+                                  uint64_t, int32_t*, int32_t*, uint16_t*, uint16_t, int, uint64_t*, uint64_t*);   \
+    template void launch_ms_bu<T>(const Launch&, const T*, const int32_t*, int64_t, const uint64_t*, uint64_t*,    \
+                                  uint64_t*, uint64_t, const uint64_t*, int32_t*, uint16_t*, uint16_t, int,        \
+                                  uint64_t*, uint64_t*);
+MS_INST(int32_t)
+MS_INST(int64_t)
+
+}  // namespace bfsk
