@@ -120,6 +120,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
+    ap.add_argument("--batched-reps", type=int, default=3,
+                    help="timed repetitions of the 64-source batched search (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run three 1 GiB device-to-device copies (the plain copy kernel "
                          "that scales FETCH_SIZE / WRITE_SIZE counters)")
@@ -204,6 +206,30 @@ def main():
         log(f"[bench] kernel ms over timed steps: " +
             ", ".join(f"{k}={v:.2f}" for k, v in sorted(kernel_totals.items(), key=lambda x: -x[1]) if v))
 
+    batched = None
+    if args.batched_reps > 0:
+        k = min(64, len(sources))
+        log(f"[bench] batched: {k} sources per bfs_run_multi, {args.batched_reps} timed reps")
+        wsm = bfs.workspace(g, k, dev)
+        bpar = torch.empty(k * n, dtype=torch.int32, device=dev)
+        bdep = torch.empty(k * n, dtype=torch.int32, device=dev)
+        mopts = bfs.bfs_opts_default(alpha=args.alpha, beta=args.beta, timing=0)
+        bfs.bfs_run_multi(g, sources[:k], bpar, bdep, wsm, mopts, stream)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter()
+        for _ in range(args.batched_reps):
+            bfs.bfs_run_multi(g, sources[:k], bpar, bdep, wsm, mopts, stream)
+        torch.cuda.synchronize()
+        batch_s = (time.perf_counter() - t_b) / args.batched_reps
+        single_qps = args.steps / elapsed
+        batched = {"sources_per_batch": k, "batch_ms": round(batch_s * 1e3, 3),
+                   "queries_per_s": round(k / batch_s, 1), "single_source_queries_per_s": round(single_qps, 1),
+                   "speedup_vs_single": round(k / batch_s / single_qps, 3), "parent_mode": "min"}
+        log(f"[bench] batched: {batch_s * 1e3:.2f} ms per {k}-source batch -> {k / batch_s:.1f} queries/s "
+            f"(single-source: {single_qps:.1f} queries/s)")
+        del wsm, bpar, bdep
+        torch.cuda.empty_cache()
+
     if args.copy_calibration:
         src_t = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst_t = torch.empty_like(src_t)
@@ -232,6 +258,7 @@ def main():
                    "kernel_ms_total": {k: round(v, 3) for k, v in kernel_totals.items() if v}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
     g.close()
