@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--parent-mode", choices=["any", "min"], default="any")
     ap.add_argument("--alpha", type=float, default=15.0)
     ap.add_argument("--beta", type=float, default=18.0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time only the given alpha/beta and default knobs (no autotuner pass)")
+    ap.add_argument("--tune-sources", type=int, default=8, help="tuning sources (seed 99, distinct from evaluation)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel HIP events")
@@ -161,19 +164,38 @@ def main():
     stream = torch.cuda.current_stream()
     log(f"[bench] graph resident ({(d_off.numel() * d_off.element_size() + nnz * 4) / 2**30:.2f} GiB), "
         f"workspace {ws.numel() / 2**30:.2f} GiB; warmup {args.warmup}")
-    for i in range(args.warmup):
-        bfs.bfs_run(g, int(sources[i % len(sources)]), parent, depth, ws, opts, stream)
-    torch.cuda.synchronize()
 
-    log(f"[bench] timing {args.steps} steps")
-    stats = []
-    torch.cuda.synchronize()
-    t_begin = time.perf_counter()
-    for i in range(args.steps):
-        st = bfs.bfs_run(g, int(sources[i % len(sources)]), parent, depth, ws, opts, stream)
-        stats.append(st.as_dict())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_begin
+    def timed_steps(o):
+        for i in range(args.warmup):
+            bfs.bfs_run(g, int(sources[i % len(sources)]), parent, depth, ws, o, stream)
+        torch.cuda.synchronize()
+        sts = []
+        t_begin = time.perf_counter()
+        for i in range(args.steps):
+            st = bfs.bfs_run(g, int(sources[i % len(sources)]), parent, depth, ws, o, stream)
+            sts.append(st.as_dict())
+        torch.cuda.synchronize()
+        return sts, time.perf_counter() - t_begin
+
+    default_params = None
+    tuned = None
+    if not args.no_autotune and args.dir == "do":
+        from paper_1705_04590_amd import autotune
+        tsrc = graphgen.random_sources(off, args.tune_sources, seed=99)
+        t0 = time.time()
+        tuned = autotune.tune(g, tsrc, k=1)
+        log(f"[bench] autotune ({tuned['trials']} trials, {time.time() - t0:.1f}s): alpha={tuned['alpha']} "
+            f"beta={tuned['beta']} bu_serial={tuned['bu_serial']} grid={tuned['grid_blocks']} "
+            f"claim={tuned['td_claim']} ({tuned['default_ms']:.3f} -> {tuned['tuned_ms']:.3f} ms on tuning sources)")
+        log(f"[bench] timing {args.steps} steps with alpha={args.alpha} beta={args.beta} (defaults)")
+        d_stats, d_elapsed = timed_steps(opts)
+        default_params = {"value": round(m * args.steps / d_elapsed / 1e9, 3), "alpha": args.alpha,
+                          "beta": args.beta, "ms_per_step": round(d_elapsed / args.steps * 1e3, 4)}
+        log(f"[bench] defaults: {default_params['value']} GTEPS")
+        opts = autotune.opts_from(tuned, dir=0, parent_mode=opts.parent_mode, timing=opts.timing)
+
+    log(f"[bench] timing {args.steps} steps (alpha={opts.alpha} beta={opts.beta})")
+    stats, elapsed = timed_steps(opts)
     gteps = m * args.steps / elapsed / 1e9
     per_source_ms = [s["total_ms"] for s in stats]
     log(f"[bench] {args.steps} searches in {elapsed:.3f}s -> {gteps:.2f} GTEPS "
@@ -214,6 +236,12 @@ def main():
         bpar = torch.empty(k * n, dtype=torch.int32, device=dev)
         bdep = torch.empty(k * n, dtype=torch.int32, device=dev)
         mopts = bfs.bfs_opts_default(alpha=args.alpha, beta=args.beta, timing=0)
+        if tuned is not None:
+            from paper_1705_04590_amd import autotune
+            mt = autotune.tune(g, graphgen.random_sources(off, k, seed=99), k=k)
+            mopts = autotune.opts_from(mt, timing=0)
+            log(f"[bench] batched autotune: alpha={mt['alpha']} beta={mt['beta']} serial={mt['bu_serial']} "
+                f"({mt['default_ms']:.2f} -> {mt['tuned_ms']:.2f} ms)")
         bfs.bfs_run_multi(g, sources[:k], bpar, bdep, wsm, mopts, stream)
         torch.cuda.synchronize()
         t_b = time.perf_counter()
@@ -251,7 +279,10 @@ def main():
         "config": {"workload": f"kronecker_s{args.scale}_ef{args.edgefactor}_single_source_{args.dir}",
                    "scale": args.scale, "edgefactor": args.edgefactor, "n": n, "nnz": nnz, "m_undirected": m,
                    "sources": len(sources), "offsets": "int32" if use32 else "int64",
-                   "parent_mode": args.parent_mode, "alpha": args.alpha, "beta": args.beta,
+                   "parent_mode": args.parent_mode, "alpha": opts.alpha, "beta": opts.beta,
+                   "bu_serial": opts.bu_serial or 16, "grid_blocks": opts.grid_blocks or 2048,
+                   "td_claim": "cas" if opts.td_claim == 1 else "fetch_or",
+                   "tuning": "autotuned on 8 sources of seed 99" if tuned else "none",
                    "levels_p50": int(np.median([s["levels"] for s in stats])),
                    "search_ms_p50": round(float(np.percentile(per_source_ms, 50)), 3),
                    "search_ms_p99": round(float(np.percentile(per_source_ms, 99)), 3),
@@ -259,6 +290,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
+        "default_params": default_params,
     }
     print(json.dumps(out), flush=True)
     g.close()

@@ -176,9 +176,11 @@ bfs_status bfs_create_graph_dcsc(int64_t nrows, int64_t ncols, int64_t row_base,
 
 void bfs_destroy_graph(bfs_graph* g);
 
-/* Bytes of device workspace bfs_run (k = 1) or bfs_run_multi (k sources)
- * needs on this graph; for a DCSC graph, the bytes bfs_block_td and
- * bfs_block_bu need (k ignored).  Returns 0 for a bad handle or k.         */
+/* Bytes of device workspace on this graph: k = 1 gives what bfs_run needs;
+ * k = 2..64 what bfs_run_multi needs for any batch size (its layout does not
+ * depend on k, so a one-source bfs_run_multi also uses the k = 2 size); for
+ * a DCSC graph, the bytes bfs_block_td and bfs_block_bu need (k ignored).
+ * Returns 0 for a bad handle or k.                                         */
 size_t bfs_workspace_bytes(const bfs_graph* g, int k);
 
 /* Single-source search from `source` on a CSR graph (Alg. 1/2/3/4 local

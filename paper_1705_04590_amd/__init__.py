@@ -180,7 +180,8 @@ def bfs_create_graph_csr(offsets: torch.Tensor, cols: torch.Tensor, flags: int =
     h = _vp()
     _check(lib().bfs_create_graph_csr(n, po, offsets.element_size(), pc, cols.numel(), flags, _stream(stream),
                                       ctypes.byref(h)), "bfs_create_graph_csr")
-    return Graph(h, (offsets, cols), "csr", n=n, nnz=cols.numel(), flags=flags)
+    return Graph(h, (offsets, cols), "csr", n=n, nnz=cols.numel(), flags=flags,
+                 offset_bytes=offsets.element_size())
 
 
 def _opt_ptr(t, dtype, name, numel=None):

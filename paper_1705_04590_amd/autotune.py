@@ -1,0 +1,117 @@
+"""Autotuner for the tunable knobs of bfs_run / bfs_run_multi.
+
+Knobs (none changes results: depths are unique and minimum-id parents are
+direction-invariant; the GPU tests check both):
+  alpha, beta   the Section 4.4 switch thresholds
+  bu_serial     entries a lane scans alone before its wave helps (bottom-up)
+  grid_blocks   workgroup cap of the grid-stride kernels
+  td_claim      top-down claim: fetch-or on the visited bitmap or CAS on parent
+
+The search is a coordinate descent: (alpha, beta) on a grid first, then each
+remaining knob in turn, every candidate timed as the mean wall time of the
+library call over the tuning sources (drawn with a seed distinct from the
+evaluation sources).  Results are cached in a JSON file keyed by device name
+and graph class (vertex count, entry count, offset width, batch size).
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import torch
+
+from . import bfs_opts_default, bfs_run, bfs_run_multi, workspace
+
+ALPHAS = (15.0, 4.0, 8.0, 25.0, 40.0, 80.0, 160.0)
+BETAS = (18.0, 6.0, 36.0, 72.0)
+SERIALS = (16, 4, 8, 32)
+GRIDS = (2048, 1024, 4096)
+CLAIMS = (0, 1)
+
+
+def _key(g, k: int) -> str:
+    name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    return f"{name}|n={g.n}|nnz={g.nnz}|off={g.offset_bytes}|k={k}"
+
+
+def _time(fn, reps: int) -> float:
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps
+
+
+def tune(g, sources, k: int = 1, cache_path: str | None = None, reps: int = 1, verbose: bool = False) -> dict:
+    """Tune the knobs for graph g; k=1 tunes bfs_run over `sources`, k>1 tunes
+    bfs_run_multi on batches of k of them.  Returns the best settings."""
+    key = _key(g, k)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            return cache[key]
+    dev = torch.device("cuda:0")
+    n = g.n
+    if k == 1:
+        ws = workspace(g, 1, dev)
+        par = torch.empty(n, dtype=torch.int32, device=dev)
+        dep = torch.empty(n, dtype=torch.int32, device=dev)
+
+        def run(o):
+            for s in sources:
+                bfs_run(g, int(s), par, dep, ws, o)
+    else:
+        ws = workspace(g, k, dev)
+        par = torch.empty(k * n, dtype=torch.int32, device=dev)
+        dep = torch.empty(k * n, dtype=torch.int32, device=dev)
+        batch = [int(s) for s in sources[:k]]
+
+        def run(o):
+            bfs_run_multi(g, batch, par, dep, ws, o)
+
+    best = {"alpha": 15.0, "beta": 18.0, "bu_serial": 16, "grid_blocks": 2048, "td_claim": 0}
+    trials = []
+
+    def measure(cfg):
+        o = bfs_opts_default(**cfg)
+        run(o)  # warm
+        t = _time(lambda: run(o), reps)
+        trials.append((dict(cfg), t))
+        if verbose:
+            print(f"[autotune] {cfg} -> {t * 1e3:.3f} ms", flush=True)
+        return t
+
+    best_t = measure(best)
+    for a in ALPHAS:
+        for b in BETAS:
+            cfg = dict(best, alpha=a, beta=b)
+            if cfg == best:
+                continue
+            t = measure(cfg)
+            if t < best_t:
+                best, best_t = cfg, t
+    for name, values in (("bu_serial", SERIALS), ("grid_blocks", GRIDS), ("td_claim", CLAIMS if k == 1 else ())):
+        for v in values:
+            cfg = dict(best, **{name: v})
+            if cfg == best:
+                continue
+            t = measure(cfg)
+            if t < best_t:
+                best, best_t = cfg, t
+    default_t = trials[0][1]
+    result = dict(best, tuned_ms=best_t * 1e3, default_ms=default_t * 1e3, trials=len(trials))
+    if cache_path:
+        cache[key] = result
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return result
+
+
+def opts_from(result: dict, **extra):
+    cfg = {k: result[k] for k in ("alpha", "beta", "bu_serial", "grid_blocks", "td_claim") if k in result}
+    cfg.update(extra)
+    return bfs_opts_default(**cfg)

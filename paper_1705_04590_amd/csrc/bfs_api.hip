@@ -66,11 +66,32 @@ struct bfs_graph {
     uint64_t* d_iso = nullptr;
     int64_t isolated = 0;
     // host metadata
-    uint64_t* h_buf = nullptr;              // pinned: counter readback
-    std::vector<hipEvent_t> events;         // timing pool
+    uint64_t* h_buf = nullptr;              // pinned: create-time readback only
 };
 
 namespace {
+
+// Per-thread host state of a running search: a pinned buffer for counter
+// readback and a pool of timing events.  Keeping it per thread (not per graph)
+// lets several threads search the same graph at once on their own streams.
+struct HostCtx {
+    uint64_t* pinned = nullptr;
+    std::vector<hipEvent_t> events;
+    ~HostCtx() {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        if (pinned) (void)hipHostFree(pinned);
+    }
+};
+thread_local HostCtx tl_ctx;
+
+hipError_t host_ctx(HostCtx** out) {
+    if (!tl_ctx.pinned) {
+        hipError_t e = hipHostMalloc((void**)&tl_ctx.pinned, 4096, hipHostMallocDefault);
+        if (e != hipSuccess) { tl_ctx.pinned = nullptr; return e; }
+    }
+    *out = &tl_ctx;
+    return hipSuccess;
+}
 
 // -------------------------------------------------------------- workspace layout
 struct SingleLayout {
@@ -178,7 +199,7 @@ size_t multi_bytes(const bfs_graph* g, int) { return multi_layout(g).total; }
 
 // -------------------------------------------------------------- timing
 struct Timer {
-    bfs_graph* g;
+    HostCtx* g;
     hipStream_t s;
     bool on;
     struct Rec { int kind; int level; size_t ev; };
@@ -246,10 +267,12 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     const int claim_mode = o.parent_mode == BFS_PARENT_MIN ? CLAIM_MIN : (o.td_claim == 1 ? CLAIM_CAS : CLAIM_BITMAP);
     const int serial = o.bu_serial > 0 ? o.bu_serial : 16;
     Launch L{stream, o.grid_blocks > 0 ? o.grid_blocks : 2048};
-    Timer T{g, stream, o.timing != 0, {}, 0};
+    HostCtx* ctx = nullptr;
+    HIP_TRY(host_ctx(&ctx));
+    Timer T{ctx, stream, o.timing != 0, {}, 0};
 
     // degree of the source: the first frontier's edge count
-    uint64_t* h = g->h_buf;
+    uint64_t* h = ctx->pinned;
     OffT* hoff = (OffT*)h;
     HIP_TRY(hipMemcpyAsync(hoff, (const char*)g->off + sizeof(OffT) * src, 2 * sizeof(OffT), hipMemcpyDeviceToHost,
                            stream));
@@ -394,8 +417,10 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
     const uint64_t full = k == 64 ? ~0ull : ((1ull << k) - 1);
     const int serial = o.bu_serial > 0 ? o.bu_serial : 16;
     Launch L{stream, o.grid_blocks > 0 ? o.grid_blocks : 2048};
-    Timer T{g, stream, o.timing != 0, {}, 0};
-    uint64_t* h = g->h_buf;
+    HostCtx* ctx = nullptr;
+    HIP_TRY(host_ctx(&ctx));
+    Timer T{ctx, stream, o.timing != 0, {}, 0};
+    uint64_t* h = ctx->pinned;
 
     // sources travel through the pinned buffer (k <= 64 ids)
     std::memcpy(h, h_src, sizeof(int64_t) * (size_t)k);
@@ -528,6 +553,10 @@ bfs_status build_isolated(bfs_graph* g, hipStream_t s) {
 }
 
 }  // namespace
+
+namespace bfsk {
+int64_t graph_vertices(const bfs_graph* g) { return (g && g->kind == KIND_CSR) ? g->n : 0; }
+}  // namespace bfsk
 
 // ================================================================== C ABI
 extern "C" {
@@ -695,7 +724,6 @@ bfs_status bfs_create_graph_dcsc(int64_t nrows, int64_t ncols, int64_t row_base,
 
 void bfs_destroy_graph(bfs_graph* g) {
     if (!g) return;
-    for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
     if (g->d_iso) (void)hipFree(g->d_iso);
     if (g->h_buf) (void)hipHostFree(g->h_buf);
     delete g;

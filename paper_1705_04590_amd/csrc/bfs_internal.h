@@ -5,7 +5,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct bfs_graph;
+
 namespace bfsk {
+
+// number of vertices of a CSR graph handle (0 for other handles)
+int64_t graph_vertices(const bfs_graph* g);
 
 constexpr int WAVE = 64;
 constexpr int TD_BLOCK = 256;                 // threads per top-down expand workgroup

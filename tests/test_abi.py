@@ -8,8 +8,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    src = open(os.path.join(ROOT, "include", "bfs.h")).read()
+def declared_functions(header="bfs.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(bfs_[a-z_]+)\s*\(", src)))
 
@@ -27,6 +27,22 @@ def test_library_exports_every_declared_symbol():
     for name in declared_functions():
         assert hasattr(lib, name), name
         assert name in bfs.EXPORTED, name
+
+
+def test_library_exports_every_server_symbol():
+    import paper_1705_04590_amd as bfs
+    lib = bfs.lib()
+    names = declared_functions("bfs_serve.h")
+    assert "bfs_server_submit" in names and "bfs_server_replay" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_server_options_defaults_need_no_gpu():
+    from paper_1705_04590_amd import serve
+    o = serve.bfs_server_opts_default()
+    assert (o.slots, o.max_batch, o.want_parent) == (4, 64, 0)
+    assert o.opts.alpha == 15.0 and o.hbm_budget == 8 << 30
 
 
 def test_host_side_defaults_and_strings():
