@@ -103,8 +103,109 @@ def cpu_baseline(off, cols, sources, m, max_seconds):
                       f"{t_total:.1f} s"}
 
 
+SERVE_GRAPHS = [("kron14", "kron", 14, 1), ("kron16", "kron", 16, 1), ("kron18", "kron", 18, 1),
+                ("kron20", "kron", 20, 1), ("kron22", "kron", 22, 1), ("kron24", "kron", 24, 1),
+                ("er20_deg8", "er", 20, 1), ("grid1024", "grid", 1024, 0), ("grid2048", "grid", 2048, 0),
+                ("kron18_s2", "kron", 18, 2), ("kron20_s2", "kron", 20, 2), ("kron22_s2", "kron", 22, 2)]
+
+
+def serve_bench(args):
+    """Served queries over 12 resident graphs: Poisson arrivals, continuous batching vs one query per launch."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1705_04590_amd as bfs
+    from paper_1705_04590_amd import serve
+
+    dev = torch.device("cuda:0")
+    graphs, keep = [], []
+    t0 = time.time()
+    for name, kind, p, seed in SERVE_GRAPHS:
+        if kind == "kron":
+            off, cols = graphgen.kronecker(p, 16, seed=seed)
+        elif kind == "er":
+            off, cols = graphgen.erdos_renyi(1 << p, 8.0, seed=seed)
+        else:
+            off, cols = graphgen.grid2d(p, p)
+        d_off, d_cols = torch.from_numpy(off).to(dev), torch.from_numpy(cols).to(dev)
+        g = bfs.bfs_create_graph_csr(d_off, d_cols, bfs.BFS_GRAPH_SYMMETRIC | bfs.BFS_GRAPH_SORTED)
+        srcs = graphgen.random_sources(off, 256, seed=6)
+        graphs.append((name, g, srcs, off.size - 1, int(off[-1])))
+        keep.append((d_off, d_cols))
+    log(f"[serve] {len(graphs)} graphs resident in {time.time() - t0:.1f}s: " +
+        ", ".join(f"{x[0]}(n={x[3]})" for x in graphs))
+    rng = np.random.default_rng(6)
+
+    def stream(m, rate):
+        gaps = rng.exponential(1e6 / rate, m)
+        t = np.cumsum(gaps) - gaps[0]
+        gi = rng.integers(0, len(graphs), m).astype(np.int32)
+        src = np.array([graphs[g][2][rng.integers(0, 256)] for g in gi], dtype=np.int64)
+        return t, gi, src
+
+    def run(t, gi, src, slots, max_batch):
+        o = serve.bfs_server_opts_default(slots=slots, max_batch=max_batch, hbm_budget=args.serve_budget_gib << 30)
+        srv = serve.Server(o)
+        for x in graphs:
+            srv.bfs_server_add_graph(x[1])
+        srv.bfs_server_replay(t, gi, src, np.arange(t.size))
+        srv.bfs_server_drain()
+        st = srv.bfs_server_stats_get()
+        srv.bfs_server_destroy()
+        return st
+
+    m = args.serve_requests
+    # capacity of one query per launch: everything arrives at once, FIFO, one
+    # slot, batches of one (bfs_run); a short pilot sizes the measured run to
+    # about `serve_seconds`
+    t, gi, src = stream(m, 1e9)
+    pilot = run(np.zeros(32), gi[:32], src[:32], 1, 1)["queries_per_s"]
+    m1 = int(min(m, max(64, pilot * args.serve_seconds)))
+    log(f"[serve] pilot {pilot:.0f} q/s -> {m1} queries for the one-per-launch capacity run")
+    cap1 = run(np.zeros(m1), gi[:m1], src[:m1], 1, 1)["queries_per_s"]
+    capb = run(np.zeros(m), gi, src, args.serve_slots, 64)["queries_per_s"]
+    log(f"[serve] capacity: one query per launch {cap1:.0f} q/s, batched {capb:.0f} q/s")
+    rows = []
+    for f in args.serve_rates:
+        rate = f * cap1
+        # arrivals span about serve_seconds; the one-per-launch server needs
+        # about serve_seconds * max(f, 1) to work through them
+        mr = int(min(m, max(64, rate * args.serve_seconds / max(f, 1.0))))
+        t, gi, src = stream(mr, rate)
+        single = run(t, gi, src, 1, 1)
+        log(f"[serve] {f:>4}x ({mr} queries at {rate:.0f}/s): one-per-launch {single['queries_per_s']:.0f} q/s "
+            f"p50 {single['p50_us'] / 1e3:.2f} ms p99 {single['p99_us'] / 1e3:.2f} ms")
+        batched = run(t, gi, src, args.serve_slots, 64)
+        rows.append({"rate_x_single_capacity": f, "offered_qps": round(rate, 1), "requests": mr,
+                     "batched": {k: round(batched[k], 2) for k in ("queries_per_s", "p50_us", "p99_us",
+                                                                    "mean_batch", "max_inflight")},
+                     "one_query_per_launch": {k: round(single[k], 2) for k in ("queries_per_s", "p50_us",
+                                                                                "p99_us")}})
+        log(f"[serve] {f:>4}x: batched {batched['queries_per_s']:.0f} q/s p50 {batched['p50_us'] / 1e3:.2f} ms "
+            f"p99 {batched['p99_us'] / 1e3:.2f} ms (batch {batched['mean_batch']:.1f}, inflight "
+            f"{batched['max_inflight']})")
+    out = {"metric": "served BFS queries/s and p50/p99 latency, 12 resident graphs, Poisson arrivals",
+           "value": round(capb, 1), "unit": "queries/s", "n_gpus": 1, "steps": m, "warmup": 0,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+           "data": "synthetic",
+           "config": {"workload": "serve_12_graphs", "graphs": [x[0] for x in graphs], "max_requests_per_rate": m,
+                      "slots": args.serve_slots, "max_batch": 64, "hbm_budget_gib": args.serve_budget_gib,
+                      "capacity_one_query_per_launch_qps": round(cap1, 1), "capacity_batched_qps": round(capb, 1)},
+           "rates": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--workload", choices=["single", "serve"], default="single",
+                    help="single: the headline single-source benchmark; serve: the query-server benchmark")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rates", type=float, nargs="+", default=[0.3, 1.0, 3.0, 10.0])
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
+                    help="approximate span of each serve run (sizes the request count per rate)")
+    ap.add_argument("--serve-budget-gib", type=int, default=64)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=2)
@@ -134,6 +235,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is described "
               "in DESIGN.md and not built", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serve":
+        serve_bench(args)
+        return
 
     import numpy as np
     import torch

@@ -101,7 +101,11 @@ typedef struct {
     int32_t grid_blocks;   /* cap on workgroups of grid-stride kernels (0 = default) */
     int32_t td_claim;      /* ANY parents, top-down claim: 0 = atomic fetch-or on a
                               claim bitmap, 1 = compare-and-swap on parent[]     */
-    int32_t reserved[8];
+    int32_t small_edges;   /* top-down levels with at most this many frontier
+                              edges run back to back inside one persistent
+                              workgroup with no host round trip (0 = default
+                              65536, negative = never)                           */
+    int32_t reserved[7];
 } bfs_opts;
 
 typedef struct {

@@ -7,7 +7,8 @@
  * Whenever a worker slot is free, the server picks the graph whose oldest
  * waiting query arrived first, takes up to `max_batch` of that graph's
  * waiting queries and runs them as one multi-source search (bfs_run_multi,
- * one bit per query in per-vertex uint64 masks).  Each slot has its own
+ * one bit per query in per-vertex uint64 masks); a batch of one query runs
+ * the single-source search (bfs_run, minimum-id parents).  Each slot has its own
  * HIP stream and host thread, so batches of different slots run on the
  * device at the same time.  A batch is admitted only when its workspace and
  * outputs fit in what is left of the server's device-memory budget (one

@@ -95,7 +95,7 @@ hipError_t host_ctx(HostCtx** out) {
 
 // -------------------------------------------------------------- workspace layout
 struct SingleLayout {
-    size_t counters, visited, vprev, fbits, nbits, claim, q0, q1, scan, tiles, partial, total;
+    size_t counters, small, rec, visited, vprev, fbits, nbits, claim, q0, q1, scan, tiles, partial, total;
 };
 
 SingleLayout single_layout(const bfs_graph* g) {
@@ -105,6 +105,8 @@ SingleLayout single_layout(const bfs_graph* g) {
     const int64_t ntiles = (g->nnz + TD_TILE - 1) / TD_TILE;
     size_t o = 0;
     L.counters = o; o = align_up(o + sizeof(uint64_t) * SLOTS * SLOT_WORDS);
+    L.small = o; o = align_up(o + sizeof(SmallState));
+    L.rec = o; o = align_up(o + sizeof(int64_t) * 4 * BFS_STATS_MAX_LEVELS);
     L.visited = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
     L.vprev = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
     L.fbits = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
@@ -290,7 +292,11 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     const uint64_t* qlen_dev = nullptr;   // set when the queue came from a bitmap conversion
     int64_t unvisited = n - 1;
     int cur_dir = (o.dir == BFS_DIR_BU) ? 1 : 0;
-    bool fmt_queue = true;   // frontier as queue (true) or only as bitmap (false); fbits always holds it
+    bool fmt_queue = true;   // frontier as queue (true) or only as bitmap (false)
+    bool fbits_stale = false;   // after the small-frontier engine fbits lags the queue
+    const int64_t small_cap = o.small_edges < 0 ? -1 : (o.small_edges == 0 ? 65536 : o.small_edges);
+    SmallState* d_small = (SmallState*)(ws + Lo.small);
+    int64_t* d_rec = (int64_t*)(ws + Lo.rec);
     int level = 0;
     int64_t reached = 1, examined = 0;
     for (;;) {
@@ -299,6 +305,62 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
         else if (o.dir == BFS_DIR_BU) cur_dir = 1;
         else if (cur_dir == 0) { if ((double)m_f * o.alpha > (double)m_u) cur_dir = 1; }
         else { if ((double)n_f * o.beta < (double)n) cur_dir = 0; }
+
+        // ---- small top-down levels: run them back to back on the device
+        if (cur_dir == 0 && fmt_queue && !qlen_dev && m_f > 0 && small_cap >= 0 && m_f <= small_cap) {
+            SmallState hs{};
+            hs.qlen = qlen; hs.n_f = n_f; hs.m_f = m_f; hs.m_u = m_u;
+            hs.level = level; hs.cur_is_b = 0;
+            std::memcpy(h, &hs, sizeof(hs));
+            HIP_TRY(hipMemcpyAsync(d_small, h, sizeof(hs), hipMemcpyHostToDevice, stream));
+            const int rec_cap = (st && level < BFS_STATS_MAX_LEVELS) ? BFS_STATS_MAX_LEVELS - level : 0;
+            // forced top-down never switches: with alpha = 0 the rule m_f * alpha > m_u cannot fire
+            const double eng_alpha = o.dir == BFS_DIR_TD ? 0.0 : o.alpha;
+            HIP_TRY(T.begin());
+            launch_td_small<OffT>(L, claim_mode, off, g->cols, parent, depth, visited, vprev, claim, qcur, qnext, n,
+                                  d_small, d_rec, rec_cap, eng_alpha, small_cap, (int64_t)1 << 40);
+            // the engine leaves the counter slots alone and the level index moves
+            // on: clear every slot for the per-level kernels that may follow
+            launch_clear_words(L, counters, SLOTS * SLOT_WORDS);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(T.end(BFS_K_TD_EXPAND, -1));
+            HIP_TRY(hipMemcpyAsync(h, d_small, sizeof(hs), hipMemcpyDeviceToHost, stream));
+            if (rec_cap > 0)
+                HIP_TRY(hipMemcpyAsync(h + 64, d_rec, sizeof(int64_t) * 4 * (size_t)rec_cap, hipMemcpyDeviceToHost,
+                                       stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            std::memcpy(&hs, h, sizeof(hs));
+            if (st) {
+                st->launches[BFS_K_TD_EXPAND] += 1;
+                st->launches[BFS_K_CONVERT] += 1;
+                st->td_levels += (int32_t)hs.levels_done;
+                int64_t unv = unvisited;
+                const int64_t* r = (const int64_t*)(h + 64);
+                for (int64_t i = 0; i < hs.levels_done && i < rec_cap; ++i, r += 4) {
+                    const int lv = level + (int)i;
+                    st->level_dir[lv] = 0;
+                    st->level_nf[lv] = r[0];
+                    st->level_mf[lv] = r[1];
+                    st->level_mu[lv] = r[2];
+                    st->level_unvisited[lv] = unv;
+                    st->level_examined[lv] = r[1];
+                    unv -= r[3];
+                }
+            }
+            examined += hs.examined;
+            reached += hs.found;
+            unvisited -= hs.found;
+            level += (int)hs.levels_done;
+            if (hs.cur_is_b) { int32_t* t = qcur; qcur = qnext; qnext = t; }
+            fbits_stale = true;
+            if (hs.reason == 0) break;   // the next frontier is empty
+            qlen = hs.qlen;
+            n_f = hs.n_f;
+            m_f = hs.m_f;
+            m_u = hs.m_u;
+            if (level > n + 1) return fail(BFS_E_HIP, "level loop did not terminate");
+            continue;   // the host decides the next level
+        }
 
         uint64_t* slot = counters + (size_t)(level % SLOTS) * SLOT_WORDS;
         uint64_t* zslot = counters + (size_t)((level + 1) % SLOTS) * SLOT_WORDS;
@@ -328,6 +390,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                 HIP_TRY(hipGetLastError());
                 HIP_TRY(T.end(BFS_K_TD_EXPAND, level));
                 HIP_TRY(T.begin());
+                fbits_stale = false;
                 launch_merge(L, claim_mode == CLAIM_MIN, visited, vprev, claim, fbits, W);
                 HIP_TRY(hipGetLastError());
                 HIP_TRY(T.end(BFS_K_CONVERT, level));
@@ -340,6 +403,15 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             // with m_f == 0 nothing is launched: the slot was cleared by the
             // previous level (or by init) and reads as an empty next frontier
         } else {
+            if (fbits_stale) {
+                HIP_TRY(T.begin());
+                launch_clear_words(L, fbits, W);
+                launch_queue_to_bitmap(L, qcur, qlen, fbits);
+                HIP_TRY(hipGetLastError());
+                HIP_TRY(T.end(BFS_K_CONVERT, level));
+                if (st) st->launches[BFS_K_CONVERT] += 2;
+                fbits_stale = false;
+            }
             fmt_queue = false;
             HIP_TRY(T.begin());
             launch_bu_sweep<OffT>(L, off, g->cols, fbits, nbits, visited, vprev, parent, depth, n, W, next_depth,

@@ -67,6 +67,19 @@ void launch_bu_sweep(const Launch& L, const OffT* off, const int32_t* cols, cons
                      int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot);
 
 void launch_clear_words(const Launch& L, uint64_t* w, int64_t nw);
+void launch_queue_to_bitmap(const Launch& L, const int32_t* q, int64_t qlen, uint64_t* bits);
+
+// small-frontier engine state (device memory, read and written by the engine)
+struct SmallState {
+    int64_t qlen, n_f, m_f, m_u, level, cur_is_b;   // in/out
+    int64_t levels_done, reason;                    // out: 0 empty, 1 -> bottom-up, 2 edge cap, 3 level cap
+    int64_t found, examined;                        // out: vertices discovered, entries expanded
+};
+template <typename OffT>
+void launch_td_small(const Launch& L, int mode, const OffT* off, const int32_t* cols, int32_t* parent,
+                     int32_t* depth, uint64_t* visited, uint64_t* vprev, uint64_t* claim, int32_t* qa, int32_t* qb,
+                     int64_t n, SmallState* st, int64_t* rec, int rec_cap, double alpha, int64_t edge_cap,
+                     int64_t max_levels);
 void launch_bitmap_to_queue(const Launch& L, const uint64_t* bits, int64_t W, int32_t* q, uint64_t* qlen_ctr);
 void launch_merge(const Launch& L, bool min_mode, uint64_t* visited, uint64_t* vprev, uint64_t* claim,
                   uint64_t* fnext, int64_t W);

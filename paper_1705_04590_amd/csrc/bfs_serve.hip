@@ -107,12 +107,14 @@ struct bfs_server {
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 
     // workspace of a multi-source search (its layout does not depend on k)
-    size_t multi_ws(int32_t gid) const { return bfs_workspace_bytes(graphs[gid], 2); }
+    // a batch of one runs the single-source search (bfs_run), larger batches
+    // the multi-source one; both give minimum-id parents
+    size_t ws_for(int32_t gid, int k) const { return bfs_workspace_bytes(graphs[gid], k == 1 ? 1 : 2); }
 
     size_t batch_bytes(int32_t gid, int k) const {
         const int64_t n = graph_n[gid];
-        const size_t ws = multi_ws(gid);
-        const size_t outs = (size_t)k * (size_t)n * sizeof(int32_t) * (o.want_parent ? 2 : 1);
+        const size_t ws = ws_for(gid, k);
+        const size_t outs = (size_t)k * (size_t)n * sizeof(int32_t) * ((o.want_parent || k == 1) ? 2 : 1);
         return Pool::round(ws) + Pool::round(outs);
     }
 
@@ -181,13 +183,20 @@ struct bfs_server {
             const int k = (int)batch.size();
             const int64_t n = graph_n[gid];
             char* chunk = pool.base + off;
-            const size_t ws_bytes = multi_ws(gid);
+            const size_t ws_bytes = ws_for(gid, k);
             int32_t* depth = (int32_t*)(chunk + Pool::round(ws_bytes));
-            int32_t* parent = o.want_parent ? depth + (size_t)k * (size_t)n : nullptr;
-            srcs.resize(k);
-            for (int j = 0; j < k; ++j) srcs[j] = batch[j].src;
-            bfs_status st = bfs_run_multi(graphs[gid], srcs.data(), k, &o.opts, parent, depth, chunk, ws_bytes,
-                                          stream, nullptr);
+            int32_t* parent = (o.want_parent || k == 1) ? depth + (size_t)k * (size_t)n : nullptr;
+            bfs_status st;
+            if (k == 1) {
+                bfs_opts so = o.opts;
+                so.parent_mode = BFS_PARENT_MIN;
+                st = bfs_run(graphs[gid], batch[0].src, &so, parent, depth, chunk, ws_bytes, stream, nullptr);
+            } else {
+                srcs.resize(k);
+                for (int j = 0; j < k; ++j) srcs[j] = batch[j].src;
+                st = bfs_run_multi(graphs[gid], srcs.data(), k, &o.opts, parent, depth, chunk, ws_bytes, stream,
+                                   nullptr);
+            }
             if (st == BFS_OK) {
                 bool copied = false;
                 for (int j = 0; j < k; ++j) {

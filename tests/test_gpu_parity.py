@@ -297,3 +297,52 @@ def test_config3_scale26_full_size(orc):
     res = orc.validate(off, cols, s, p, d)
     assert res[0] == "ok", res
     _progress("scale 26: done")
+
+
+SMALL_CAPS = (-1, 1, 7, 100, 4096, 0, 1 << 30)
+
+
+@pytest.mark.parametrize("name", ["grid", "path", "kron12", "er", "pieces"])
+def test_small_frontier_engine_cap_invariance(orc, graphs, name):
+    """The persistent small-frontier engine (any edge cap, or switched off with
+    a negative cap) changes neither results nor the per-level schedule and
+    counters."""
+    for off_dtype in (np.int32, np.int64):
+        dg = get(graphs, name, off_dtype)
+        for s in sources_for(dg.off, k=2, seed=21):
+            ref = orc.bfs_min(dg.off, dg.cols, int(s))
+            for dirv in (bfs.BFS_DIR_DO, bfs.BFS_DIR_TD):
+                base = None
+                for cap in SMALL_CAPS:
+                    for pm, claim in ((bfs.BFS_PARENT_MIN, 0), (bfs.BFS_PARENT_ANY, 0), (bfs.BFS_PARENT_ANY, 1)):
+                        p, d, st = dg.run(s, dir=dirv, parent_mode=pm, td_claim=claim, small_edges=cap)
+                        check(orc, dg, s, p, d, pm == bfs.BFS_PARENT_MIN, ref)
+                        L = min(st.levels, bfs.STATS_MAX_LEVELS)
+                        sig = (st.levels, st.reached, st.edges_examined, st.td_levels, st.bu_levels,
+                               list(st.level_dir[:L]), list(st.level_nf[:L]), list(st.level_mf[:L]),
+                               list(st.level_mu[:L]), list(st.level_unvisited[:L]), list(st.level_examined[:L]))
+                        if base is None:
+                            base = sig
+                        assert sig == base, (cap, pm, claim)
+
+
+def test_grid_many_levels_closed_form(orc):
+    """A 300x700 grid from a corner (998 levels) and from an interior point:
+    depths follow the Manhattan distance and minimum-id parents the closed form
+    (up if below the source row, else left / right toward the source column,
+    else down)."""
+    H, W = 300, 700
+    off, cols = graphgen.grid2d(H, W)
+    dg = DevGraph(off, cols, np.int32)
+    r, c = np.divmod(np.arange(H * W), W)
+    for (r0, c0) in ((0, 0), (123, 456), (H - 1, W - 1)):
+        s = r0 * W + c0
+        dist = np.abs(r - r0) + np.abs(c - c0)
+        par = np.where(r > r0, s * 0 + (r - 1) * W + c,
+                       np.where(c > c0, r * W + c - 1, np.where(c < c0, r * W + c + 1, (r + 1) * W + c)))
+        par[s] = s
+        for dirv in (bfs.BFS_DIR_DO, bfs.BFS_DIR_TD, bfs.BFS_DIR_BU):
+            p, d, st = dg.run(s, dir=dirv, parent_mode=bfs.BFS_PARENT_MIN)
+            assert np.array_equal(d, dist)
+            assert np.array_equal(p, par)
+            assert st.levels == int(dist.max()) + 1

@@ -84,8 +84,9 @@ def test_tight_budget_queues_and_loses_nothing():
     gs = graphs()
     big = [gs[1]]
     n = big[0][0].size - 1
-    # room for one single-query batch only: every batch shrinks to one query and they run one at a time
-    one = bfs.bfs_workspace_bytes(big[0][4], 2) + 2 * 4 * n + 4096
+    # room for one single-query batch only (single-source workspace plus depth
+    # and parent): every batch shrinks to one query and they run one at a time
+    one = bfs.bfs_workspace_bytes(big[0][4], 1) + 2 * 4 * n + 4096
     reqs = [(0, int(s)) for s in graphgen.random_sources(big[0][0], 40, seed=1)]
     outs, st, (ids, lat, bsz, seq) = run_mix(big, reqs, slots=4, max_batch=64, want_parent=1, hbm_budget=one)
     assert st["completed"] == 40 and st["max_inflight"] == 1 and st["batches"] == 40
