@@ -104,7 +104,7 @@ typedef struct {
     int32_t small_edges;   /* top-down levels with at most this many frontier
                               edges run back to back inside one persistent
                               workgroup with no host round trip (0 = default
-                              65536, negative = never)                           */
+                              4096, negative = never)                            */
     int32_t reserved[7];
 } bfs_opts;
 

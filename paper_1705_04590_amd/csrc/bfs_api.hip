@@ -65,6 +65,8 @@ struct bfs_graph {
     // of vertices without entries, ids >= n in the last word set; their count
     uint64_t* d_iso = nullptr;
     int64_t isolated = 0;
+    // row heads for the bottom-up step: {degree, first three entries} per vertex
+    int4* d_head = nullptr;
     // host metadata
     uint64_t* h_buf = nullptr;              // pinned: create-time readback only
 };
@@ -294,7 +296,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     int cur_dir = (o.dir == BFS_DIR_BU) ? 1 : 0;
     bool fmt_queue = true;   // frontier as queue (true) or only as bitmap (false)
     bool fbits_stale = false;   // after the small-frontier engine fbits lags the queue
-    const int64_t small_cap = o.small_edges < 0 ? -1 : (o.small_edges == 0 ? 65536 : o.small_edges);
+    const int64_t small_cap = o.small_edges < 0 ? -1 : (o.small_edges == 0 ? 4096 : o.small_edges);
     SmallState* d_small = (SmallState*)(ws + Lo.small);
     int64_t* d_rec = (int64_t*)(ws + Lo.rec);
     int level = 0;
@@ -414,17 +416,17 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             }
             fmt_queue = false;
             HIP_TRY(T.begin());
-            launch_bu_sweep<OffT>(L, off, g->cols, fbits, nbits, visited, vprev, parent, depth, n, W, next_depth,
-                                  serial, slot, zslot);
+            launch_bu_sweep<OffT>(L, g->d_head, off, g->cols, fbits, nbits, visited, vprev, parent, depth, W,
+                                  next_depth, serial, slot, zslot);
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_BU_SWEEP, level));
             if (st) st->launches[BFS_K_BU_SWEEP] += 1;
         }
         HIP_TRY(hipMemcpyAsync(h, slot, sizeof(uint64_t) * SLOT_WORDS, hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
-        const int64_t n_next = (int64_t)h[S_NNEXT];
-        const int64_t m_next = (int64_t)h[S_MNEXT];
-        const int64_t lvl_examined = cur_dir == 0 ? m_f : (int64_t)h[S_EXAMINED];
+        const int64_t n_next = (int64_t)slot_sum(h, S_NNEXT);
+        const int64_t m_next = (int64_t)slot_sum(h, S_MNEXT);
+        const int64_t lvl_examined = cur_dir == 0 ? m_f : (int64_t)slot_sum(h, S_EXAMINED);
         examined += lvl_examined;
         if (st && level < BFS_STATS_MAX_LEVELS) {
             st->level_dir[level] = (int8_t)cur_dir;
@@ -506,7 +508,7 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
     HIP_TRY(hipStreamSynchronize(stream));
     if (st) st->launches[BFS_K_INIT] += 2;
 
-    int64_t n_f = (int64_t)h[M_SLOT_NNEXT], m_f = (int64_t)h[M_SLOT_MNEXT];
+    int64_t n_f = (int64_t)slot_sum(h, M_SLOT_NNEXT), m_f = (int64_t)slot_sum(h, M_SLOT_MNEXT);
     int64_t qlen = (int64_t)h[M_SLOT_QLEN];   // frontier vertices with edges (all of them after level 0)
     int64_t m_u = g->nnz - (k == 1 ? m_f : 0);
     int cur_dir = (o.dir == BFS_DIR_BU) ? 1 : 0;
@@ -555,8 +557,8 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
         }
         HIP_TRY(hipMemcpyAsync(h, slot, sizeof(uint64_t) * SLOT_WORDS, hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
-        const int64_t n_next = (int64_t)h[M_SLOT_NNEXT], m_next = (int64_t)h[M_SLOT_MNEXT];
-        const int64_t lvl_exam = cur_dir == 0 ? m_f + (int64_t)h[M_SLOT_EXAM] : (int64_t)h[M_SLOT_EXAM];
+        const int64_t n_next = (int64_t)slot_sum(h, M_SLOT_NNEXT), m_next = (int64_t)slot_sum(h, M_SLOT_MNEXT);
+        const int64_t lvl_exam = cur_dir == 0 ? m_f + (int64_t)slot_sum(h, M_SLOT_EXAM) : (int64_t)slot_sum(h, M_SLOT_EXAM);
         examined += lvl_exam;
         if (st && level < BFS_STATS_MAX_LEVELS) {
             st->level_dir[level] = (int8_t)cur_dir;
@@ -588,7 +590,7 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
         ++level;
         if (n_next == 0) break;
         reached_pairs += n_next;
-        m_u -= (int64_t)h[M_SLOT_MFULL];
+        m_u -= (int64_t)slot_sum(h, M_SLOT_MFULL);
         n_f = n_next;
         m_f = m_next;
     }
@@ -610,7 +612,7 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
 }
 
 template <typename OffT>
-bfs_status build_isolated(bfs_graph* g, hipStream_t s) {
+bfs_status build_derived(bfs_graph* g, hipStream_t s) {
     const int64_t W = (g->n + 63) / 64;
     HIP_TRY(hipMalloc((void**)&g->d_iso, sizeof(uint64_t) * (size_t)(W + 1)));
     uint64_t* d_count = g->d_iso + W;
@@ -621,6 +623,10 @@ bfs_status build_isolated(bfs_graph* g, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(g->h_buf, d_count, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     g->isolated = (int64_t)g->h_buf[0];
+    HIP_TRY(hipMalloc((void**)&g->d_head, sizeof(int4) * (size_t)g->n));
+    launch_row_heads<OffT>(L, (const OffT*)g->off, g->cols, g->n, g->d_head);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
     return BFS_OK;
 }
 
@@ -720,8 +726,8 @@ bfs_status bfs_create_graph_csr(int64_t n, const void* d_offsets, int offset_byt
     }
     // only in a symmetric graph is a vertex without row entries unreachable
     if (n > 0 && (g->flags & BFS_GRAPH_SYMMETRIC)) {
-        bfs_status bs = g->off_bytes == 4 ? build_isolated<int32_t>(g, (hipStream_t)hip_stream)
-                                          : build_isolated<int64_t>(g, (hipStream_t)hip_stream);
+        bfs_status bs = g->off_bytes == 4 ? build_derived<int32_t>(g, (hipStream_t)hip_stream)
+                                          : build_derived<int64_t>(g, (hipStream_t)hip_stream);
         if (bs != BFS_OK) {
             bfs_destroy_graph(g);
             return bs;
@@ -797,6 +803,7 @@ bfs_status bfs_create_graph_dcsc(int64_t nrows, int64_t ncols, int64_t row_base,
 void bfs_destroy_graph(bfs_graph* g) {
     if (!g) return;
     if (g->d_iso) (void)hipFree(g->d_iso);
+    if (g->d_head) (void)hipFree(g->d_head);
     if (g->h_buf) (void)hipHostFree(g->h_buf);
     delete g;
 }

@@ -1,0 +1,236 @@
+// Bottom-up step (Alg. 2): every unvisited vertex scans its row in stored
+// (ascending) order against the frontier bitmap and stops at the first hit,
+// which becomes its parent.  With sorted rows the first hit is the smallest
+// frontier neighbour, so this step also yields minimum-id parents.
+//
+// On a large level the step is bound by the rate of random probes into the
+// frontier bitmap (n/8 bytes: larger than one XCD's L2 at scale 26) and by
+// chains of dependent accesses (row head -> probe -> offsets -> columns ->
+// probe), so the layout keeps both short:
+//   * row heads, one 16-byte record per vertex {deg, c0, c1, c2}: the degree
+//     and the first three entries of the row (unused slots -1).  Most
+//     vertices of a large bottom-up level meet a frontier neighbour among
+//     their first three entries; only the others read offsets and columns.
+//     The heads of the next 64 vertices are loaded while the current 64 probe.
+//   * the visited bitmap is read a group of GW consecutive words at a time
+//     (one word per lane); the unvisited vertices of the group are compacted
+//     in LDS, in vertex order, and processed 64 at a time, one per lane, so
+//     sparse levels do not spend a wave per nearly-full word.
+//   * rows that continue past their head are scanned four entries per step
+//     (four column loads, then four probes, all independent), up to
+//     `serial_len` entries; rows still open after that are finished by the
+//     whole wave, one row at a time, 64 entries per step.  The first hit in
+//     row order is kept in every case.
+//   * visited words are streamed with non-temporal loads so they do not push
+//     the frontier bitmap out of L2.
+//   * next-frontier bits of the group collect in LDS (atomic or on 64-bit
+//     LDS words) and each word of nbits / visited / vprev is written once by
+//     its lane: no global atomics.
+#include "bfs_device.h"
+
+namespace bfsk {
+
+constexpr int BU_WIN = 512;   // compacted-list window per wave (entries)
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ bool bit_of(uint64_t word, int32_t c) { return (word >> (c & 63)) & 1ull; }
+
+__device__ __forceinline__ uint64_t stream_load(const uint64_t* p) { return __builtin_nontemporal_load(p); }
+
+template <typename OffT>
+__global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
+    const int4* __restrict__ head, const OffT* __restrict__ off, const int32_t* __restrict__ cols,
+    const uint64_t* __restrict__ fbits, uint64_t* __restrict__ nbits, uint64_t* __restrict__ visited,
+    uint64_t* __restrict__ vprev, int32_t* __restrict__ parent, int32_t* __restrict__ depth, int64_t W, int GW,
+    int32_t next_depth, int serial_len, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot) {
+    __shared__ int32_t s_list[BU_BLOCK / WAVE][BU_WIN];
+    __shared__ unsigned long long s_nb[BU_BLOCK / WAVE][WAVE];
+    zero_slot(zslot);
+    const int lane = lane_id();
+    const int wid = threadIdx.x / WAVE;
+    int32_t* list = s_list[wid];
+    unsigned long long* nbw = s_nb[wid];
+    const int64_t G = (W + GW - 1) / GW;
+    const int64_t nwaves = (int64_t)gridDim.x * (BU_BLOCK / WAVE);
+    uint64_t my_n = 0, my_m = 0, my_x = 0;
+    int64_t w0 = 0;
+    // v found its parent at row position pos
+    auto found = [&](int32_t v, int32_t par, int32_t pos, int32_t deg) {
+        parent[v] = par;
+        depth[v] = next_depth;
+        atomicOr(&nbw[(v >> 6) - w0], 1ull << (v & 63));
+        my_n += 1;
+        my_m += (uint64_t)deg;
+        my_x += (uint64_t)(pos + 1);
+    };
+    for (int64_t gi = (int64_t)blockIdx.x * (BU_BLOCK / WAVE) + wid; gi < G; gi += nwaves) {
+        w0 = gi * GW;
+        const int64_t w = w0 + lane;
+        const bool mine = lane < GW && w < W;
+        const uint64_t wv = mine ? stream_load(&visited[w]) : ~0ull;
+        const int cnt = __popcll(~wv);
+        const int incl = wave_incl_scan(cnt);
+        const int tot = __shfl(incl, WAVE - 1, WAVE);
+        nbw[lane] = 0;
+        for (int lo = 0; lo < tot; lo += BU_WIN) {
+            const int hi = min(lo + BU_WIN, tot);
+            const int nw = hi - lo;
+            // this lane's unvisited vertices with list index in [lo, hi)
+            int idx = incl - cnt;
+            if (cnt && idx < hi && idx + cnt > lo) {
+                uint64_t x = ~wv;
+                for (; idx < lo; ++idx) x &= x - 1;
+                for (; x && idx < hi; ++idx) {
+                    const int b = __ffsll((unsigned long long)x) - 1;
+                    x &= x - 1;
+                    list[idx - lo] = (int32_t)(w * WAVE + b);
+                }
+            }
+            wave_lds_sync();
+            // heads of the first round; later rounds are prefetched one ahead
+            int32_t v_next = lane < nw ? list[lane] : 0;
+            int4 h_next = make_int4(0, -1, -1, -1);
+            if (lane < nw) h_next = head[v_next];
+            for (int r = 0; r < nw; r += WAVE) {
+                const bool act = r + lane < nw;
+                const int32_t v = v_next;
+                const int4 h = h_next;
+                if (r + WAVE + lane < nw) {
+                    v_next = list[r + WAVE + lane];
+                    h_next = head[v_next];
+                }
+                const int deg = act ? h.x : 0;
+                int32_t par = -1;
+                int32_t pos = 0;   // position of the hit in the row
+                if (deg > 0 && bit_of(fbits[h.y >> 6], h.y)) { par = h.y; pos = 0; }
+                else if (deg > 1 && bit_of(fbits[h.z >> 6], h.z)) { par = h.z; pos = 1; }
+                else if (deg > 2 && bit_of(fbits[h.w >> 6], h.w)) { par = h.w; pos = 2; }
+                // continuation: positions relative to the row start (rows hold < 2^31 entries)
+                int64_t beg = 0;
+                int32_t rp = deg;   // next entry to scan; deg when nothing is left
+                if (par < 0 && deg > 3) {
+                    beg = (int64_t)off[v];
+                    const int32_t lim = deg - 3 > serial_len ? 3 + serial_len : deg;
+                    const int32_t* row = cols + beg;
+                    for (rp = 3; rp < lim; rp += 4) {
+                        // four entries at once: loads first, then probes
+                        const int32_t c0 = row[rp];
+                        const int32_t c1 = rp + 1 < lim ? row[rp + 1] : -1;
+                        const int32_t c2 = rp + 2 < lim ? row[rp + 2] : -1;
+                        const int32_t c3 = rp + 3 < lim ? row[rp + 3] : -1;
+                        const uint64_t f0 = fbits[c0 >> 6];
+                        const uint64_t f1 = c1 >= 0 ? fbits[c1 >> 6] : 0ull;
+                        const uint64_t f2 = c2 >= 0 ? fbits[c2 >> 6] : 0ull;
+                        const uint64_t f3 = c3 >= 0 ? fbits[c3 >> 6] : 0ull;
+                        if (bit_of(f0, c0)) { par = c0; break; }
+                        if (c1 >= 0 && bit_of(f1, c1)) { par = c1; rp += 1; break; }
+                        if (c2 >= 0 && bit_of(f2, c2)) { par = c2; rp += 2; break; }
+                        if (c3 >= 0 && bit_of(f3, c3)) { par = c3; rp += 3; break; }
+                    }
+                    if (par >= 0) pos = rp;
+                    else if (rp > lim) rp = lim;
+                }
+                uint64_t rem = __ballot(par < 0 && rp < deg);
+                while (rem) {
+                    const int l = __ffsll((unsigned long long)rem) - 1;
+                    rem &= rem - 1;
+                    const int32_t* row = cols + __shfl(beg, l, WAVE);
+                    const int32_t pb = __shfl(rp, l, WAVE);
+                    const int32_t pe = __shfl(deg, l, WAVE);
+                    int32_t got = -1, gotpos = pe;
+                    for (int32_t b = pb; b < pe; b += WAVE) {
+                        const int32_t i = b + lane;
+                        bool hit = false;
+                        int32_t c = 0;
+                        if (i < pe) {
+                            c = row[i];
+                            hit = bit_of(fbits[c >> 6], c);
+                        }
+                        const uint64_t hm = __ballot(hit);
+                        if (hm) {
+                            const int f = __ffsll((unsigned long long)hm) - 1;
+                            got = __shfl(c, f, WAVE);
+                            gotpos = b + f;
+                            break;
+                        }
+                    }
+                    if (lane == l) {
+                        par = got;
+                        if (got >= 0) pos = gotpos;
+                    }
+                }
+                if (par >= 0) found(v, par, pos, deg);
+                else if (act) my_x += (uint64_t)deg;
+            }
+            wave_lds_sync();
+        }
+        const uint64_t nb = nbw[lane];
+        if (mine) {
+            nbits[w] = nb;
+            if (nb) {
+                visited[w] = wv | nb;
+                vprev[w] = wv | nb;
+            }
+        }
+        wave_lds_sync();
+    }
+    uint64_t* ln = slot_line(slot);
+    block_add3<BU_BLOCK / WAVE>(my_n, my_m, my_x, &ln[S_NNEXT], &ln[S_MNEXT], &ln[S_EXAMINED]);
+}
+
+// words per group: 64 when that still gives every wave of the grid several
+// groups, fewer on small graphs so the sweep spreads over the whole chip
+static int group_words(int64_t W, int waves) {
+    int gw = WAVE;
+    while (gw > 1 && (W + gw - 1) / gw < 2 * (int64_t)waves) gw >>= 1;
+    return gw;
+}
+
+template <typename OffT>
+void launch_bu_sweep(const Launch& L, const int4* head, const OffT* off, const int32_t* cols, const uint64_t* fbits,
+                     uint64_t* nbits, uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W,
+                     int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot) {
+    const int gw = group_words(W, L.grid_cap * (BU_BLOCK / WAVE));
+    const int64_t G = (W + gw - 1) / gw;
+    const int g = grid_for(G, BU_BLOCK / WAVE, L.grid_cap);
+    hipLaunchKernelGGL(k_bu_sweep<OffT>, dim3(g), dim3(BU_BLOCK), 0, L.stream, head, off, cols, fbits, nbits,
+                       visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot, zslot);
+}
+
+// ------------------------------------------------------------------ row heads
+template <typename OffT>
+__global__ void k_row_heads(const OffT* __restrict__ off, const int32_t* __restrict__ cols, int64_t n,
+                            int4* __restrict__ head) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const int64_t b = (int64_t)off[v];
+        const int64_t d = (int64_t)off[v + 1] - b;
+        int4 h;
+        h.x = (int32_t)d;
+        h.y = d > 0 ? cols[b] : -1;
+        h.z = d > 1 ? cols[b + 1] : -1;
+        h.w = d > 2 ? cols[b + 2] : -1;
+        head[v] = h;
+    }
+}
+
+template <typename OffT>
+void launch_row_heads(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, int4* head) {
+    hipLaunchKernelGGL(k_row_heads<OffT>, dim3(grid_for(n, 256, L.grid_cap)), dim3(256), 0, L.stream, off, cols, n,
+                       head);
+}
+
+#define BFS_BU_INST(T)                                                                                           \
+    template void launch_bu_sweep<T>(const Launch&, const int4*, const T*, const int32_t*, const uint64_t*,      \
+                                     uint64_t*, uint64_t*, uint64_t*, int32_t*, int32_t*, int64_t, int32_t, int, \
+                                     uint64_t*, uint64_t*);                                                      \
+    template void launch_row_heads<T>(const Launch&, const T*, const int32_t*, int64_t, int4*);
+BFS_BU_INST(int32_t)
+BFS_BU_INST(int64_t)
+
+}  // namespace bfsk

@@ -25,6 +25,17 @@ __device__ __forceinline__ T wave_incl_scan(T x) {
     return x;
 }
 
+// this workgroup's line of a counter slot
+__device__ __forceinline__ uint64_t* slot_line(uint64_t* slot) {
+    return slot + (blockIdx.x % SLOT_SPREAD) * SLOT_LINE;
+}
+
+// workgroup 0 clears a whole counter slot
+__device__ __forceinline__ void zero_slot(uint64_t* zslot) {
+    if (blockIdx.x == 0 && zslot)
+        for (int i = threadIdx.x; i < SLOT_WORDS; i += blockDim.x) zslot[i] = 0;
+}
+
 // Sum of (a, b, c) over the workgroup, added once to three counters.
 template <int NWAVES>
 __device__ __forceinline__ void block_add3(uint64_t a, uint64_t b, uint64_t c, uint64_t* ca, uint64_t* cb,

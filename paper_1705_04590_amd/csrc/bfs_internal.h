@@ -23,7 +23,21 @@ constexpr int BU_BLOCK = 256;                 // 4 waves, one 64-vertex word per
 
 // Per-level counter slot (uint64 words).  A ring of SLOTS slots lets level
 // d write slot d % SLOTS while any kernel of level d clears slot (d+1) % SLOTS.
-enum { S_QLEN = 0, S_NNEXT = 1, S_MNEXT = 2, S_EXAMINED = 3, SLOT_WORDS = 8, SLOTS = 3 };
+// A slot is SLOT_SPREAD lines of SLOT_LINE words.  Sums that every workgroup
+// adds to (S_NNEXT, S_MNEXT, S_EXAMINED) go to line blockIdx % SLOT_SPREAD of
+// their word, and the host adds the lines up: one address taking an atomic
+// from each of thousands of workgroups serialises them.  Counters whose
+// running value matters on the device (the queue append position S_QLEN,
+// word 4 = queue length of a conversion) live in line 0 only.
+enum { S_QLEN = 0, S_NNEXT = 1, S_MNEXT = 2, S_EXAMINED = 3, SLOT_LINE = 16, SLOT_SPREAD = 16,
+       SLOT_WORDS = SLOT_LINE * SLOT_SPREAD, SLOTS = 3 };
+
+// sum of word `w` over the lines of a slot copied to the host
+inline uint64_t slot_sum(const uint64_t* h, int w) {
+    uint64_t s = 0;
+    for (int j = 0; j < SLOT_SPREAD; ++j) s += h[j * SLOT_LINE + w];
+    return s;
+}
 
 // Validation error bits.
 enum { VE_OFFSETS = 1, VE_RANGE = 2, VE_UNSORTED = 4, VE_ASYM = 8 };
@@ -62,9 +76,12 @@ void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t*
                       int32_t next_depth);
 
 template <typename OffT>
-void launch_bu_sweep(const Launch& L, const OffT* off, const int32_t* cols, const uint64_t* fbits, uint64_t* nbits,
-                     uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t n, int64_t W,
+void launch_bu_sweep(const Launch& L, const int4* head, const OffT* off, const int32_t* cols, const uint64_t* fbits,
+                     uint64_t* nbits, uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W,
                      int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot);
+// per-vertex row heads {degree, first three entries (-1 when absent)}
+template <typename OffT>
+void launch_row_heads(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, int4* head);
 
 void launch_clear_words(const Launch& L, uint64_t* w, int64_t nw);
 void launch_queue_to_bitmap(const Launch& L, const int32_t* q, int64_t qlen, uint64_t* bits);
@@ -85,6 +102,8 @@ void launch_merge(const Launch& L, bool min_mode, uint64_t* visited, uint64_t* v
                   uint64_t* fnext, int64_t W);
 
 // ---- multi-source --------------------------------------------------------
+// NNEXT, MNEXT, MFULL and EXAM are spread over the slot's lines; QLEN, OR and
+// CONV live in line 0.
 enum { M_SLOT_QLEN = 0, M_SLOT_NNEXT = 1, M_SLOT_MNEXT = 2, M_SLOT_OR = 3, M_SLOT_MFULL = 4, M_SLOT_EXAM = 5,
        M_SLOT_CONV = 6 };
 

@@ -61,6 +61,8 @@ __global__ void k_init(int32_t* __restrict__ parent, int32_t* __restrict__ depth
                        uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev, uint64_t* __restrict__ fbits,
                        uint64_t* __restrict__ claim, const uint64_t* __restrict__ iso, int64_t W,
                        int32_t* __restrict__ queue, int64_t src, uint64_t* __restrict__ counters) {
+    // every output entry is written here, whole lines at a time; the search
+    // then overwrites the reached ones
     int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = tid; v < n; v += stride) {
@@ -80,7 +82,7 @@ __global__ void k_init(int32_t* __restrict__ parent, int32_t* __restrict__ depth
         claim[w] = 0;
     }
     if (tid == 0) queue[0] = (int32_t)src;
-    if (tid < SLOTS * SLOT_WORDS) counters[tid] = 0;
+    for (int64_t i = tid; i < SLOTS * SLOT_WORDS; i += stride) counters[i] = 0;
 }
 
 void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, uint64_t* visited, uint64_t* vprev,
@@ -111,16 +113,19 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
     __shared__ int32_t s_start[TD_TILE + 1];   // first edge of staged vertex j, relative to the tile
     __shared__ int64_t s_base[TD_TILE + 1];    // off[u_j] - scan[j]: cols index = s_base[j] + edge index
     __shared__ int32_t s_u[TD_TILE + 1];
-    __shared__ int32_t s_out[TD_TILE];
+    // winners of several tiles collect here; the buffer is flushed to the next
+    // queue with one global atomic whenever less than a tile's worth is free
+    __shared__ int32_t s_out[2 * TD_TILE];
     __shared__ int s_cnt;
     __shared__ uint64_t s_qbase;
 
-    if (blockIdx.x == 0 && threadIdx.x < SLOT_WORDS && zslot) zslot[threadIdx.x] = 0;
+    zero_slot(zslot);
     const int64_t qlen = len_of(qlen_dev, qlen_host);
     const int64_t total = total_dev ? *total_dev : total_host;
     const int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
     uint64_t my_n = 0, my_m = 0;
     const int lane = lane_id();
+    if (threadIdx.x == 0) s_cnt = 0;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int64_t e0 = t * TD_TILE;
         const int64_t e1 = (e0 + TD_TILE < total) ? e0 + TD_TILE : total;
@@ -139,7 +144,6 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
             s_base[j] = (int64_t)off[u] - sc;
             s_u[j] = u;
         }
-        if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
         // the thread's TD_EPT edges move through each stage together so their
         // loads and atomics are in flight at the same time
@@ -215,13 +219,18 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
         }
         __syncthreads();
         const int cnt = s_cnt;
-        if (threadIdx.x == 0 && cnt > 0)
-            s_qbase = atomicAdd((unsigned long long*)&slot[S_QLEN], (unsigned long long)cnt);
-        __syncthreads();
-        for (int j = threadIdx.x; j < cnt; j += TD_BLOCK) qnext[s_qbase + j] = s_out[j];
+        if (cnt > TD_TILE || t + gridDim.x >= ntiles) {
+            if (threadIdx.x == 0 && cnt > 0)
+                s_qbase = atomicAdd((unsigned long long*)&slot[S_QLEN], (unsigned long long)cnt);
+            __syncthreads();
+            for (int j = threadIdx.x; j < cnt; j += TD_BLOCK) qnext[s_qbase + j] = s_out[j];
+            __syncthreads();
+            if (threadIdx.x == 0) s_cnt = 0;
+        }
         __syncthreads();
     }
-    block_add3<TD_BLOCK / WAVE>(my_n, my_m, 0, &slot[S_NNEXT], &slot[S_MNEXT], nullptr);
+    uint64_t* ln = slot_line(slot);
+    block_add3<TD_BLOCK / WAVE>(my_n, my_m, 0, &ln[S_NNEXT], &ln[S_MNEXT], nullptr);
 }
 
 template <typename OffT>
@@ -241,100 +250,6 @@ void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t*
     else if (mode == CLAIM_CAS) BFS_EXPAND(CLAIM_CAS);
     else BFS_EXPAND(CLAIM_BITMAP);
 #undef BFS_EXPAND
-}
-
-// ------------------------------------------------------------------ bottom-up sweep
-template <typename OffT>
-__global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
-    const OffT* __restrict__ off, const int32_t* __restrict__ cols, const uint64_t* __restrict__ fbits,
-    uint64_t* __restrict__ nbits, uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev,
-    int32_t* __restrict__ parent,
-    int32_t* __restrict__ depth, int64_t n, int64_t W, int32_t next_depth, int serial_len,
-    uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot) {
-    if (blockIdx.x == 0 && threadIdx.x < SLOT_WORDS && zslot) zslot[threadIdx.x] = 0;
-    const int lane = lane_id();
-    const int64_t nwaves = (int64_t)gridDim.x * (BU_BLOCK / WAVE);
-    uint64_t my_n = 0, my_m = 0, my_x = 0;
-    for (int64_t w = (int64_t)blockIdx.x * (BU_BLOCK / WAVE) + threadIdx.x / WAVE; w < W; w += nwaves) {
-        const uint64_t vis = visited[w];
-        if (vis == ~0ull) {
-            if (lane == 0) nbits[w] = 0;
-            continue;
-        }
-        const int64_t v = w * WAVE + lane;
-        const bool active = !((vis >> lane) & 1ull);
-        int64_t beg = 0, end = 0;
-        if (active) {
-            beg = (int64_t)off[v];
-            end = (int64_t)off[v + 1];
-        }
-        int64_t p = beg;
-        const int64_t lim = (end - beg > serial_len) ? beg + serial_len : end;
-        int32_t par = -1;
-        // one probe per step: most rows hit within the first two entries, and
-        // every probe moves a line of the frontier bitmap
-        while (p < lim) {
-            const int32_t c = cols[p];
-            if ((fbits[c >> 6] >> (c & 63)) & 1ull) { par = c; break; }
-            ++p;
-        }
-        // rows still open after the serial part: the whole wave scans them,
-        // one at a time, 64 entries per step, first hit in row order
-        uint64_t rem = __ballot(active && par < 0 && p < end);
-        while (rem) {
-            const int l = __ffsll((unsigned long long)rem) - 1;
-            rem &= rem - 1;
-            const int64_t pb = __shfl(p, l, WAVE);
-            const int64_t pe = __shfl(end, l, WAVE);
-            int32_t got = -1;
-            int64_t gotpos = pe;
-            for (int64_t b = pb; b < pe; b += WAVE) {
-                const int64_t idx = b + lane;
-                bool hit = false;
-                int32_t c = 0;
-                if (idx < pe) {
-                    c = cols[idx];
-                    hit = (fbits[c >> 6] >> (c & 63)) & 1ull;
-                }
-                const uint64_t hm = __ballot(hit);
-                if (hm) {
-                    const int f = __ffsll((unsigned long long)hm) - 1;
-                    got = __shfl(c, f, WAVE);
-                    gotpos = b + f;
-                    break;
-                }
-            }
-            if (lane == l) { par = got; p = gotpos; }
-        }
-        const bool found = par >= 0;
-        const uint64_t fm = __ballot(found);
-        if (lane == 0) {
-            nbits[w] = fm;
-            if (fm) {
-                visited[w] = vis | fm;
-                vprev[w] = vis | fm;
-            }
-        }
-        if (found) {
-            parent[v] = par;
-            depth[v] = next_depth;
-            my_n += 1;
-            my_m += (uint64_t)(end - beg);
-            my_x += (uint64_t)(p - beg + 1);
-        } else if (active) {
-            my_x += (uint64_t)(end - beg);
-        }
-    }
-    block_add3<BU_BLOCK / WAVE>(my_n, my_m, my_x, &slot[S_NNEXT], &slot[S_MNEXT], &slot[S_EXAMINED]);
-}
-
-template <typename OffT>
-void launch_bu_sweep(const Launch& L, const OffT* off, const int32_t* cols, const uint64_t* fbits, uint64_t* nbits,
-                     uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t n, int64_t W,
-                     int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot) {
-    int g = grid_for(W, BU_BLOCK / WAVE, L.grid_cap);
-    hipLaunchKernelGGL(k_bu_sweep<OffT>, dim3(g), dim3(BU_BLOCK), 0, L.stream, off, cols, fbits, nbits, visited,
-                       vprev, parent, depth, n, W, next_depth, serial_len, slot, zslot);
 }
 
 // ------------------------------------------------------------------ conversions
@@ -474,9 +389,6 @@ void launch_validate_csr(const Launch& L, const OffT* off, const int32_t* cols, 
                                       const uint64_t*, int64_t, const int64_t*, const int32_t*, int64_t,        \
                                       int32_t*, int32_t*, uint64_t*, uint64_t*, int32_t*, uint64_t*,            \
                                       uint64_t*, int32_t);                                                      \
-    template void launch_bu_sweep<T>(const Launch&, const T*, const int32_t*, const uint64_t*, uint64_t*,      \
-                                     uint64_t*, uint64_t*, int32_t*, int32_t*, int64_t, int64_t, int32_t, int,  \
-                                     uint64_t*, uint64_t*);                                                     \
     template void launch_validate_csr<T>(const Launch&, const T*, const int32_t*, int64_t, int64_t, uint32_t,  \
                                          uint32_t*);
 BFS_INST(int32_t)

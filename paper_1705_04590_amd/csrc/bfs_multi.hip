@@ -38,11 +38,12 @@ __device__ __forceinline__ void or_reduce_add(uint64_t n, uint64_t m, uint64_t o
         for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) {
             a += red[0][i]; b += red[1][i]; c |= red[2][i]; e += red[3][i]; x += red[4][i];
         }
-        if (a) atomicAdd((unsigned long long*)&slot[M_NNEXT], (unsigned long long)a);
-        if (b) atomicAdd((unsigned long long*)&slot[M_MNEXT], (unsigned long long)b);
+        uint64_t* ln = slot_line(slot);
+        if (a) atomicAdd((unsigned long long*)&ln[M_NNEXT], (unsigned long long)a);
+        if (b) atomicAdd((unsigned long long*)&ln[M_MNEXT], (unsigned long long)b);
         if (c) atomicOr((unsigned long long*)&slot[M_OR], (unsigned long long)c);
-        if (e) atomicAdd((unsigned long long*)&slot[M_MFULL], (unsigned long long)e);
-        if (x) atomicAdd((unsigned long long*)&slot[M_EXAM], (unsigned long long)x);
+        if (e) atomicAdd((unsigned long long*)&ln[M_MFULL], (unsigned long long)e);
+        if (x) atomicAdd((unsigned long long*)&ln[M_EXAM], (unsigned long long)x);
     }
 }
 
@@ -68,7 +69,8 @@ __global__ void k_ms_init(int64_t n, uint64_t full, const uint64_t* __restrict__
         F[v] = 0;
         N[v] = 0;
     }
-    if (blockIdx.x == 0 && threadIdx.x < SLOTS * SLOT_WORDS) counters[threadIdx.x] = 0;
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < SLOTS * SLOT_WORDS; i += blockDim.x) counters[i] = 0;
 }
 
 // one workgroup of 64 threads: thread j seeds source j, the first thread of
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(TD_BLOCK) void k_ms_td_expand(
     __shared__ int32_t s_out[TD_TILE];
     __shared__ int s_cnt;
     __shared__ uint64_t s_qbase;
-    if (blockIdx.x == 0 && threadIdx.x < SLOT_WORDS && zslot) zslot[threadIdx.x] = 0;
+    zero_slot(zslot);
     const int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
     const int lane = lane_id();
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(256) void k_ms_bu_sweep(const OffT* __restrict__ of
                                                      int32_t* __restrict__ par_vm, uint16_t* __restrict__ lvl_vm,
                                                      uint16_t level, int serial, uint64_t* __restrict__ slot,
                                                      uint64_t* __restrict__ zslot) {
-    if (blockIdx.x == 0 && threadIdx.x < SLOT_WORDS && zslot) zslot[threadIdx.x] = 0;
+    zero_slot(zslot);
     const uint64_t active = *active_dev;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     uint64_t cn = 0, cm = 0, cor = 0, cfull = 0, cx = 0;
