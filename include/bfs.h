@@ -104,8 +104,13 @@ typedef struct {
     int32_t small_edges;   /* top-down levels with at most this many frontier
                               edges run back to back inside one persistent
                               workgroup with no host round trip (0 = default
-                              4096, negative = never)                            */
-    int32_t reserved[7];
+                              4096, negative = no persistent engine at all)      */
+    int32_t persist_edges; /* ... and up to this many inside persist_groups
+                              workgroups separated by grid barriers (0 = default
+                              262144)                                            */
+    int32_t persist_groups;/* workgroups of that engine (0 = default 256; capped
+                              by what fits on the device at once)                */
+    int32_t reserved[5];
 } bfs_opts;
 
 typedef struct {

@@ -44,7 +44,8 @@ class bfs_opts(ctypes.Structure):
     _fields_ = [("dir", ctypes.c_int32), ("parent_mode", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("timing", ctypes.c_int32), ("bu_serial", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("td_claim", ctypes.c_int32), ("small_edges", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("persist_edges", ctypes.c_int32), ("persist_groups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class bfs_stats(ctypes.Structure):

@@ -6,6 +6,7 @@ direction-invariant; the GPU tests check both):
   bu_serial     entries a lane scans alone before its wave helps (bottom-up)
   grid_blocks   workgroup cap of the grid-stride kernels
   td_claim      top-down claim: fetch-or on the visited bitmap or CAS on parent
+  small_edges   persistent top-down engine on (0, default caps) or off (-1)
 
 The search is a coordinate descent: (alpha, beta) on a grid first, then each
 remaining knob in turn, every candidate timed as the mean wall time of the
@@ -28,6 +29,7 @@ BETAS = (18.0, 6.0, 36.0, 72.0)
 SERIALS = (16, 4, 8, 32)
 GRIDS = (2048, 1024, 4096)
 CLAIMS = (0, 1)
+ENGINE = (0, -1)
 
 
 def _key(g, k: int) -> str:
@@ -73,7 +75,7 @@ def tune(g, sources, k: int = 1, cache_path: str | None = None, reps: int = 1, v
         def run(o):
             bfs_run_multi(g, batch, par, dep, ws, o)
 
-    best = {"alpha": 15.0, "beta": 18.0, "bu_serial": 16, "grid_blocks": 2048, "td_claim": 0}
+    best = {"alpha": 15.0, "beta": 18.0, "bu_serial": 16, "grid_blocks": 2048, "td_claim": 0, "small_edges": 0}
     trials = []
 
     def measure(cfg):
@@ -94,7 +96,8 @@ def tune(g, sources, k: int = 1, cache_path: str | None = None, reps: int = 1, v
             t = measure(cfg)
             if t < best_t:
                 best, best_t = cfg, t
-    for name, values in (("bu_serial", SERIALS), ("grid_blocks", GRIDS), ("td_claim", CLAIMS if k == 1 else ())):
+    for name, values in (("bu_serial", SERIALS), ("grid_blocks", GRIDS), ("td_claim", CLAIMS if k == 1 else ()),
+                         ("small_edges", ENGINE if k == 1 else ())):
         for v in values:
             cfg = dict(best, **{name: v})
             if cfg == best:
@@ -112,6 +115,7 @@ def tune(g, sources, k: int = 1, cache_path: str | None = None, reps: int = 1, v
 
 
 def opts_from(result: dict, **extra):
-    cfg = {k: result[k] for k in ("alpha", "beta", "bu_serial", "grid_blocks", "td_claim") if k in result}
+    cfg = {k: result[k] for k in ("alpha", "beta", "bu_serial", "grid_blocks", "td_claim", "small_edges")
+           if k in result}
     cfg.update(extra)
     return bfs_opts_default(**cfg)

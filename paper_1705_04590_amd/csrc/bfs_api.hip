@@ -67,6 +67,8 @@ struct bfs_graph {
     int64_t isolated = 0;
     // row heads for the bottom-up step: {degree, first three entries} per vertex
     int4* d_head = nullptr;
+    // workgroups of the persistent top-down engine that fit on the device
+    int persist_groups_max = 1;
     // host metadata
     uint64_t* h_buf = nullptr;              // pinned: create-time readback only
 };
@@ -97,7 +99,8 @@ hipError_t host_ctx(HostCtx** out) {
 
 // -------------------------------------------------------------- workspace layout
 struct SingleLayout {
-    size_t counters, small, rec, visited, vprev, fbits, nbits, claim, q0, q1, scan, tiles, partial, total;
+    size_t counters, pctl, pctr, small, ctl_end, rec, visited, vprev, fbits, nbits, claim, q0, q1, scan, tiles, partial,
+        total;
 };
 
 SingleLayout single_layout(const bfs_graph* g) {
@@ -106,8 +109,14 @@ SingleLayout single_layout(const bfs_graph* g) {
     const int64_t W = (n + 63) / 64;
     const int64_t ntiles = (g->nnz + TD_TILE - 1) / TD_TILE;
     size_t o = 0;
+    // control block, cleared as one range: level counters, engine barrier
+    // words and counters, engine state; the engine's level records follow
+    // the state so one copy brings both back
     L.counters = o; o = align_up(o + sizeof(uint64_t) * SLOTS * SLOT_WORDS);
+    L.pctl = o; o = align_up(o + sizeof(PersistCtl));
+    L.pctr = o; o = align_up(o + sizeof(uint64_t) * SLOTS * SLOT_WORDS);
     L.small = o; o = align_up(o + sizeof(SmallState));
+    L.ctl_end = o;
     L.rec = o; o = align_up(o + sizeof(int64_t) * 4 * BFS_STATS_MAX_LEVELS);
     L.visited = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
     L.vprev = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
@@ -284,7 +293,8 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     const int64_t deg_s = (int64_t)hoff[1] - (int64_t)hoff[0];
 
     HIP_TRY(T.begin());
-    launch_init(L, parent, depth, n, visited, vprev, fbits, claim, g->d_iso, W, qcur, src, counters);
+    launch_init(L, parent, depth, n, visited, vprev, fbits, claim, g->d_iso, W, qcur, src, counters,
+                (int64_t)((Lo.ctl_end - Lo.counters) / sizeof(uint64_t)));
     HIP_TRY(hipGetLastError());
     HIP_TRY(T.end(BFS_K_INIT, -1));
     if (st) st->launches[BFS_K_INIT] += 1;
@@ -296,7 +306,14 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     int cur_dir = (o.dir == BFS_DIR_BU) ? 1 : 0;
     bool fmt_queue = true;   // frontier as queue (true) or only as bitmap (false)
     bool fbits_stale = false;   // after the small-frontier engine fbits lags the queue
-    const int64_t small_cap = o.small_edges < 0 ? -1 : (o.small_edges == 0 ? 4096 : o.small_edges);
+    // persistent engine: one workgroup up to cap_one frontier edges, pgroups
+    // workgroups up to cap_multi (no engine when small_edges < 0)
+    bool engine_on = o.small_edges >= 0;
+    const int64_t cap_one = o.small_edges > 0 ? o.small_edges : 1024;
+    const int64_t cap_multi = o.persist_edges > 0 ? std::max<int64_t>(o.persist_edges, cap_one) : 65536;
+    int pgroups = o.persist_groups > 0 ? o.persist_groups : 64;
+    pgroups = std::min(pgroups, g->persist_groups_max);
+    if (pgroups < 1) pgroups = 1;
     SmallState* d_small = (SmallState*)(ws + Lo.small);
     int64_t* d_rec = (int64_t*)(ws + Lo.rec);
     int level = 0;
@@ -309,35 +326,44 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
         else { if ((double)n_f * o.beta < (double)n) cur_dir = 0; }
 
         // ---- small top-down levels: run them back to back on the device
-        if (cur_dir == 0 && fmt_queue && !qlen_dev && m_f > 0 && small_cap >= 0 && m_f <= small_cap) {
-            SmallState hs{};
-            hs.qlen = qlen; hs.n_f = n_f; hs.m_f = m_f; hs.m_u = m_u;
-            hs.level = level; hs.cur_is_b = 0;
-            std::memcpy(h, &hs, sizeof(hs));
-            HIP_TRY(hipMemcpyAsync(d_small, h, sizeof(hs), hipMemcpyHostToDevice, stream));
+        if (cur_dir == 0 && fmt_queue && !qlen_dev && m_f > 0 && engine_on && m_f <= cap_multi) {
+            // one workgroup while the frontier is tiny, many once it grows
+            const bool multi = m_f > cap_one;
+            const int groups = multi ? pgroups : 1;
+            SmallIn in{qlen, n_f, m_f, m_u, level};
             const int rec_cap = (st && level < BFS_STATS_MAX_LEVELS) ? BFS_STATS_MAX_LEVELS - level : 0;
             // forced top-down never switches: with alpha = 0 the rule m_f * alpha > m_u cannot fire
             const double eng_alpha = o.dir == BFS_DIR_TD ? 0.0 : o.alpha;
             HIP_TRY(T.begin());
-            launch_td_small<OffT>(L, claim_mode, off, g->cols, parent, depth, visited, vprev, claim, qcur, qnext, n,
-                                  d_small, d_rec, rec_cap, eng_alpha, small_cap, (int64_t)1 << 40);
-            // the engine leaves the counter slots alone and the level index moves
-            // on: clear every slot for the per-level kernels that may follow
-            launch_clear_words(L, counters, SLOTS * SLOT_WORDS);
+            launch_td_persist<OffT>(L, claim_mode, groups, off, g->cols, parent, depth, visited, vprev, claim, qcur,
+                                    qnext, n, in, d_small, (uint64_t*)(ws + Lo.pctr), (PersistCtl*)(ws + Lo.pctl),
+                                    d_rec, rec_cap, eng_alpha, multi ? cap_multi : cap_one, multi ? cap_one / 2 : 0,
+                                    (int64_t)1 << 40);
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_TD_EXPAND, -1));
-            HIP_TRY(hipMemcpyAsync(h, d_small, sizeof(hs), hipMemcpyDeviceToHost, stream));
-            if (rec_cap > 0)
-                HIP_TRY(hipMemcpyAsync(h + 64, d_rec, sizeof(int64_t) * 4 * (size_t)rec_cap, hipMemcpyDeviceToHost,
-                                       stream));
+            // state and level records in one copy, then the whole control
+            // block is cleared: the level counters (the level index moved on),
+            // the engine's barrier words and its state (reason 0 = not run)
+            HIP_TRY(hipMemcpyAsync(h, d_small, (Lo.rec - Lo.small) + sizeof(int64_t) * 4 * (size_t)rec_cap,
+                                   hipMemcpyDeviceToHost, stream));
+            launch_clear_words(L, counters, (int64_t)((Lo.ctl_end - Lo.counters) / sizeof(uint64_t)));
+            HIP_TRY(hipGetLastError());
             HIP_TRY(hipStreamSynchronize(stream));
+            SmallState hs;
             std::memcpy(&hs, h, sizeof(hs));
+            const int64_t* recs = (const int64_t*)((const char*)h + (Lo.rec - Lo.small));
+            if (st) st->launches[BFS_K_TD_EXPAND] += 1;
+            if (hs.reason == ENG_NOT_RUN) {
+                // the workgroups could not all be resident at once (a busy
+                // device): nothing was touched, continue level by level
+                engine_on = false;
+                continue;
+            }
+            if (hs.reason == ENG_TIMEOUT) return fail(BFS_E_HIP, "top-down engine: grid barrier timed out");
             if (st) {
-                st->launches[BFS_K_TD_EXPAND] += 1;
-                st->launches[BFS_K_CONVERT] += 1;
                 st->td_levels += (int32_t)hs.levels_done;
                 int64_t unv = unvisited;
-                const int64_t* r = (const int64_t*)(h + 64);
+                const int64_t* r = recs;
                 for (int64_t i = 0; i < hs.levels_done && i < rec_cap; ++i, r += 4) {
                     const int lv = level + (int)i;
                     st->level_dir[lv] = 0;
@@ -354,8 +380,8 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             unvisited -= hs.found;
             level += (int)hs.levels_done;
             if (hs.cur_is_b) { int32_t* t = qcur; qcur = qnext; qnext = t; }
-            fbits_stale = true;
-            if (hs.reason == 0) break;   // the next frontier is empty
+            if (hs.levels_done > 0) fbits_stale = true;
+            if (hs.reason == ENG_EMPTY) break;   // the next frontier is empty
             qlen = hs.qlen;
             n_f = hs.n_f;
             m_f = hs.m_f;
@@ -724,6 +750,7 @@ bfs_status bfs_create_graph_csr(int64_t n, const void* d_offsets, int offset_byt
             return bad;
         }
     }
+    g->persist_groups_max = g->off_bytes == 4 ? persist_max_groups<int32_t>() : persist_max_groups<int64_t>();
     // only in a symmetric graph is a vertex without row entries unreachable
     if (n > 0 && (g->flags & BFS_GRAPH_SYMMETRIC)) {
         bfs_status bs = g->off_bytes == 4 ? build_derived<int32_t>(g, (hipStream_t)hip_stream)

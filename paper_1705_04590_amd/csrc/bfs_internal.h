@@ -56,7 +56,7 @@ void launch_isolated_mask(const Launch& L, const OffT* off, int64_t n, int64_t W
 
 void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, uint64_t* visited, uint64_t* vprev,
                  uint64_t* fbits, uint64_t* claim, const uint64_t* iso, int64_t W, int32_t* queue, int64_t src,
-                 uint64_t* counters);
+                 uint64_t* counters, int64_t counter_words);
 
 // degree prefix sum of the frontier queue + tile partition for the expand
 // (scan[i] = sum of degrees of q[0..i), tile_start[t] = queue index owning
@@ -86,17 +86,33 @@ void launch_row_heads(const Launch& L, const OffT* off, const int32_t* cols, int
 void launch_clear_words(const Launch& L, uint64_t* w, int64_t nw);
 void launch_queue_to_bitmap(const Launch& L, const int32_t* q, int64_t qlen, uint64_t* bits);
 
-// small-frontier engine state (device memory, read and written by the engine)
-struct SmallState {
-    int64_t qlen, n_f, m_f, m_u, level, cur_is_b;   // in/out
-    int64_t levels_done, reason;                    // out: 0 empty, 1 -> bottom-up, 2 edge cap, 3 level cap
-    int64_t found, examined;                        // out: vertices discovered, entries expanded
+// persistent top-down engine state (device memory, read and written by the engine)
+struct SmallIn {
+    int64_t qlen, n_f, m_f, m_u, level;
 };
+// why the engine stopped; ENG_NOT_RUN (0, a cleared state) when it could not assemble
+enum { ENG_NOT_RUN = 0, ENG_EMPTY = 1, ENG_TO_BU = 2, ENG_EDGE_CAP = 3, ENG_LEVEL_CAP = 4, ENG_TIMEOUT = 5,
+       ENG_SHRINK = 6 };
+struct SmallState {                                 // written by the engine
+    int64_t qlen, n_f, m_f, m_u, level, cur_is_b;   // where the search stands
+    int64_t levels_done, reason;
+    int64_t found, examined;                        // vertices discovered, entries expanded
+};
+// grid-barrier control words, cleared before every launch
+struct PersistCtl {
+    uint32_t roll, bar, err, pad;
+};
+// most workgroups of the engine that fit on the device at once
 template <typename OffT>
-void launch_td_small(const Launch& L, int mode, const OffT* off, const int32_t* cols, int32_t* parent,
-                     int32_t* depth, uint64_t* visited, uint64_t* vprev, uint64_t* claim, int32_t* qa, int32_t* qb,
-                     int64_t n, SmallState* st, int64_t* rec, int rec_cap, double alpha, int64_t edge_cap,
-                     int64_t max_levels);
+int persist_max_groups();
+// ctr: SLOTS * SLOT_WORDS counter words and ctl: barrier words, both zero at
+// launch (the engine leaves them dirty); st reads ENG_NOT_RUN until the
+// engine writes it; rec: 4 int64 per level (n_f, m_f, m_u, n_next)
+template <typename OffT>
+void launch_td_persist(const Launch& L, int mode, int groups, const OffT* off, const int32_t* cols, int32_t* parent,
+                       int32_t* depth, uint64_t* visited, uint64_t* vprev, uint64_t* claim, int32_t* qa, int32_t* qb,
+                       int64_t n, SmallIn in, SmallState* st, uint64_t* ctr, PersistCtl* ctl, int64_t* rec,
+                       int rec_cap, double alpha, int64_t edge_cap, int64_t shrink_below, int64_t max_levels);
 void launch_bitmap_to_queue(const Launch& L, const uint64_t* bits, int64_t W, int32_t* q, uint64_t* qlen_ctr);
 void launch_merge(const Launch& L, bool min_mode, uint64_t* visited, uint64_t* vprev, uint64_t* claim,
                   uint64_t* fnext, int64_t W);

@@ -60,7 +60,8 @@ void launch_isolated_mask(const Launch& L, const OffT* off, int64_t n, int64_t W
 __global__ void k_init(int32_t* __restrict__ parent, int32_t* __restrict__ depth, int64_t n,
                        uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev, uint64_t* __restrict__ fbits,
                        uint64_t* __restrict__ claim, const uint64_t* __restrict__ iso, int64_t W,
-                       int32_t* __restrict__ queue, int64_t src, uint64_t* __restrict__ counters) {
+                       int32_t* __restrict__ queue, int64_t src, uint64_t* __restrict__ counters,
+                       int64_t counter_words) {
     // every output entry is written here, whole lines at a time; the search
     // then overwrites the reached ones
     int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -82,15 +83,15 @@ __global__ void k_init(int32_t* __restrict__ parent, int32_t* __restrict__ depth
         claim[w] = 0;
     }
     if (tid == 0) queue[0] = (int32_t)src;
-    for (int64_t i = tid; i < SLOTS * SLOT_WORDS; i += stride) counters[i] = 0;
+    for (int64_t i = tid; i < counter_words; i += stride) counters[i] = 0;
 }
 
 void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, uint64_t* visited, uint64_t* vprev,
                  uint64_t* fbits, uint64_t* claim, const uint64_t* iso, int64_t W, int32_t* queue, int64_t src,
-                 uint64_t* counters) {
+                 uint64_t* counters, int64_t counter_words) {
     int g = grid_for(n > W ? n : W, 256, L.grid_cap * 4);
     hipLaunchKernelGGL(k_init, dim3(g), dim3(256), 0, L.stream, parent, depth, n, visited, vprev, fbits, claim, iso,
-                       W, queue, src, counters);
+                       W, queue, src, counters, counter_words);
 }
 
 // ------------------------------------------------------------------ frontier degree scan

@@ -1,0 +1,372 @@
+// Persistent top-down engine: G workgroups stay resident and run consecutive
+// top-down levels (Alg. 1) with the Section 4.4 rule applied on the device,
+// separated by grid-wide barriers instead of kernel launches and host round
+// trips.  It serves the levels whose frontier is too small to fill the chip:
+// the first levels of every search and the thousands of thin levels of
+// high-diameter graphs (grids, paths).  With G = 1 the barriers reduce to
+// workgroup barriers.
+//
+// Level L:
+//   * workgroup g expands the contiguous chunk [g*C, (g+1)*C) of the queue
+//     (C = ceil(qlen / G)): the chunk's degrees are prefix-summed in LDS and
+//     its edges spread evenly over the threads (binary search over the LDS
+//     prefix).  Claims are those of the whole-graph top-down step: fetch-or on
+//     the visited bitmap (ANY), compare-and-swap on parent[] (CAS), or
+//     atomicMin on parent[] plus a claim bitmap (MIN, visited frozen for the
+//     level).
+//   * winners collect in LDS and go to the next queue with one global atomic
+//     per flush: those with out-edges at the front, those without at the back
+//     of the buffer (discovered, never expanded).
+//   * per-level counts (vertices, their degrees) go to spread counter lines.
+//   * barrier; every workgroup reads the totals and takes the same decision
+//     (stop when the next frontier is empty, when the rule switches to
+//     bottom-up, when it exceeds `edge_cap` edges or falls below
+//     `shrink_below` edges, or after `max_levels`).
+//   * the new vertices are folded into vprev (and in MIN mode into visited,
+//     clearing their claim bits, followed by a second barrier, since the next
+//     level filters on visited).  The ANY / CAS fold needs no barrier: it is
+//     done for level L by the workgroup that expands the same chunk at L + 1,
+//     and for the last level before the kernel exits.
+// The bitmaps therefore leave the engine exactly as the per-level kernels
+// leave them.  Data that other workgroups wrote during the kernel (queue
+// entries, visited words, counters) is read with device-scope atomic loads;
+// writers publish with a device-scope fence before the barrier.
+//
+// Residency: a grid barrier needs every workgroup resident at once.  The
+// kernel opens with a roll call whose wait is bounded: if not all G
+// workgroups arrive within `roll_ticks` (a busy device), the counter is
+// poisoned, every workgroup leaves before touching any search state, and the
+// host runs the level with the per-level kernels instead.  Later barriers are
+// bounded too; a timeout there sets an error flag (the state is then
+// unusable and the call fails) rather than spinning forever.
+#include "bfs_device.h"
+
+namespace bfsk {
+
+constexpr int PT_BLOCK = 256;
+constexpr int PT_WIN = 1024;             // LDS winner buffer per workgroup
+constexpr uint32_t ROLL_POISON = 1u << 30;
+
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Roll call: true when all G workgroups arrived before the deadline (then all
+// of them see true), false when the count was poisoned (then all see false).
+__device__ bool roll_call(PersistCtl* ctl, uint32_t G, long long ticks) {
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        const uint32_t old = atomicAdd(&ctl->roll, 1u);
+        int ok = -1;
+        if (old & ROLL_POISON) ok = 0;
+        const long long t0 = wall_clock64();
+        while (ok < 0) {
+            const uint32_t c = ld_dev(&ctl->roll);
+            if (c & ROLL_POISON) { ok = 0; break; }
+            if (c >= G) { ok = 1; break; }
+            if (wall_clock64() - t0 > ticks) {
+                // poison only a count that is still short; if the last
+                // workgroup arrived meanwhile the exchange fails and the
+                // next read sees G
+                if (atomicCAS(&ctl->roll, c, c | ROLL_POISON) == c) ok = 0;
+            } else {
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        s_ok = ok;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return s_ok == 1;
+}
+
+// Grid barrier number `k` (0, 1, 2, ...): false on timeout (error flag set).
+__device__ bool grid_sync(PersistCtl* ctl, uint32_t G, uint32_t k, long long ticks) {
+    __shared__ int s_ok;
+    __syncthreads();
+    if (G == 1) return true;
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        atomicAdd(&ctl->bar, 1u);
+        const uint32_t target = G * (k + 1);
+        const long long t0 = wall_clock64();
+        int ok = 1;
+        while (ld_dev(&ctl->bar) < target) {
+            if (ld_dev(&ctl->err) || wall_clock64() - t0 > ticks) {
+                atomicOr(&ctl->err, 1u);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        s_ok = ok;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+template <typename OffT, int MODE>
+__global__ __launch_bounds__(PT_BLOCK) void k_td_persist(
+    const OffT* __restrict__ off, const int32_t* __restrict__ cols, int32_t* __restrict__ parent,
+    int32_t* __restrict__ depth, uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev,
+    uint64_t* __restrict__ claim, int32_t* __restrict__ qa, int32_t* __restrict__ qb, int64_t n, SmallIn in,
+    SmallState* __restrict__ st, uint64_t* __restrict__ ctr, PersistCtl* __restrict__ ctl, int64_t* __restrict__ rec,
+    int rec_cap, double alpha, int64_t edge_cap, int64_t shrink_below, int64_t max_levels, long long roll_ticks,
+    long long bar_ticks) {
+    __shared__ int32_t s_u[PT_BLOCK];
+    __shared__ int64_t s_row[PT_BLOCK];
+    __shared__ int64_t s_pre[PT_BLOCK + 1];
+    __shared__ int64_t s_wsum[PT_BLOCK / WAVE];
+    __shared__ int32_t s_win[PT_WIN];
+    __shared__ int32_t s_win0[PT_WIN];
+    __shared__ int s_nw, s_nw0;
+    __shared__ uint64_t s_base, s_base0;
+
+    const uint32_t G = gridDim.x;
+    const uint32_t g = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    if (!roll_call(ctl, G, roll_ticks)) return;   // nothing touched yet
+
+    int64_t qlen = in.qlen, n_f = in.n_f, m_f = in.m_f, m_u = in.m_u;
+    int64_t nz_cur = 0;                            // winners without edges at the back of qcur
+    int32_t level = (int32_t)in.level;
+    int32_t* qcur = qa;
+    int32_t* qnext = qb;
+    int64_t done = 0, reason = ENG_EMPTY, found = 0, examined = 0;
+    uint32_t nbar = 0;
+    bool fail = false;
+
+    // ANY / CAS: fold a level's winners (the current queue) into vprev
+    auto fold_vprev = [&](int64_t nq, int64_t nz) {
+        const int64_t c = (nq + G - 1) / G, cz = (nz + G - 1) / G;
+        const int64_t a0 = min(nq, (int64_t)g * c), a1 = min(nq, a0 + c);
+        for (int64_t i = a0 + tid; i < a1; i += PT_BLOCK) {
+            const int32_t v = ld_dev(&qcur[i]);
+            atomicOr((unsigned long long*)&vprev[v >> 6], 1ull << (v & 63));
+        }
+        const int64_t b0 = min(nz, (int64_t)g * cz), b1 = min(nz, b0 + cz);
+        for (int64_t i = b0 + tid; i < b1; i += PT_BLOCK) {
+            const int32_t v = ld_dev(&qcur[n - 1 - i]);
+            atomicOr((unsigned long long*)&vprev[v >> 6], 1ull << (v & 63));
+        }
+    };
+
+    for (;;) {
+        if (done >= max_levels) { reason = ENG_LEVEL_CAP; break; }
+        if ((double)m_f * alpha > (double)m_u) { reason = ENG_TO_BU; break; }
+        if (m_f > edge_cap) { reason = ENG_EDGE_CAP; break; }
+        if (m_f < shrink_below) { reason = ENG_SHRINK; break; }
+        uint64_t* slot = ctr + (size_t)(done % SLOTS) * SLOT_WORDS;
+        if (tid == 0) { s_nw = 0; s_nw0 = 0; }
+        uint64_t my_n = 0, my_m = 0;
+        const int32_t next_depth = level + 1;
+        const int64_t C = (qlen + G - 1) / G;
+        const int64_t i_beg = min(qlen, (int64_t)g * C), i_end = min(qlen, i_beg + C);
+        if (MODE != CLAIM_MIN && done > 0) fold_vprev(0, nz_cur);   // back part of the previous winners
+        __syncthreads();
+        for (int64_t c0 = i_beg; c0 < i_end; c0 += PT_BLOCK) {
+            const int64_t i = c0 + tid;
+            int64_t d = 0;
+            if (i < i_end) {
+                const int32_t u = ld_dev(&qcur[i]);
+                if (MODE != CLAIM_MIN && done > 0) atomicOr((unsigned long long*)&vprev[u >> 6], 1ull << (u & 63));
+                const int64_t b = (int64_t)off[u];
+                d = (int64_t)off[u + 1] - b;
+                s_u[tid] = u;
+                s_row[tid] = b;
+            }
+            const int64_t inc = wave_incl_scan(d);
+            if (lane == WAVE - 1) s_wsum[tid / WAVE] = inc;
+            __syncthreads();
+            int64_t before = 0;
+            for (int k = 0; k < tid / WAVE; ++k) before += s_wsum[k];
+            const int64_t ex = before + inc - d;
+            s_pre[tid] = ex;
+            if (tid == PT_BLOCK - 1) s_pre[PT_BLOCK] = ex + d;
+            __syncthreads();
+            const int nv = (int)min((int64_t)PT_BLOCK, i_end - c0);
+            const int64_t E = s_pre[nv];
+            for (int64_t e0 = 0; e0 < E; e0 += PT_BLOCK) {
+                const int64_t e = e0 + tid;
+                int32_t v = 0;
+                bool won = false;
+                if (e < E) {
+                    int lo = 0, hi = nv - 1;   // last vertex whose edges start at or before e
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_pre[mid] <= e) lo = mid; else hi = mid - 1;
+                    }
+                    const int32_t u = s_u[lo];
+                    v = cols[s_row[lo] + (e - s_pre[lo])];
+                    const uint64_t bit = 1ull << (v & 63);
+                    const uint64_t vw = ld_dev(&visited[v >> 6]);
+                    if (!(vw & bit)) {
+                        if (MODE == CLAIM_MIN) {
+                            atomicMin((unsigned int*)&parent[v], (unsigned int)u);
+                            won = !(atomicOr((unsigned long long*)&claim[v >> 6], (unsigned long long)bit) & bit);
+                        } else if (MODE == CLAIM_CAS) {
+                            won = atomicCAS(&parent[v], -1, u) == -1;
+                            if (won) atomicOr((unsigned long long*)&visited[v >> 6], (unsigned long long)bit);
+                        } else {
+                            won = !(atomicOr((unsigned long long*)&visited[v >> 6], (unsigned long long)bit) & bit);
+                            if (won) parent[v] = u;
+                        }
+                    }
+                }
+                int64_t dv = 0;
+                if (won) {
+                    depth[v] = next_depth;
+                    dv = (int64_t)off[v + 1] - (int64_t)off[v];
+                    my_n += 1;
+                    my_m += (uint64_t)dv;
+                    if (dv > 0) s_win[atomicAdd(&s_nw, 1)] = v;
+                    else s_win0[atomicAdd(&s_nw0, 1)] = v;
+                }
+                __syncthreads();
+                // flush when another round could overflow a buffer
+                const int nw = s_nw, nw0 = s_nw0;
+                if (nw > PT_WIN - PT_BLOCK || nw0 > PT_WIN - PT_BLOCK) {
+                    if (tid == 0) {
+                        s_base = nw ? atomicAdd((unsigned long long*)&slot[0], (unsigned long long)nw) : 0;
+                        s_base0 = nw0 ? atomicAdd((unsigned long long*)&slot[4], (unsigned long long)nw0) : 0;
+                    }
+                    __syncthreads();
+                    for (int j = tid; j < nw; j += PT_BLOCK) qnext[s_base + j] = s_win[j];
+                    for (int j = tid; j < nw0; j += PT_BLOCK) qnext[n - 1 - (int64_t)(s_base0 + j)] = s_win0[j];
+                    __syncthreads();
+                    if (tid == 0) { s_nw = 0; s_nw0 = 0; }
+                    __syncthreads();
+                }
+            }
+            __syncthreads();
+        }
+        {
+            const int nw = s_nw, nw0 = s_nw0;
+            if (tid == 0) {
+                s_base = nw ? atomicAdd((unsigned long long*)&slot[0], (unsigned long long)nw) : 0;
+                s_base0 = nw0 ? atomicAdd((unsigned long long*)&slot[4], (unsigned long long)nw0) : 0;
+            }
+            __syncthreads();
+            for (int j = tid; j < nw; j += PT_BLOCK) qnext[s_base + j] = s_win[j];
+            for (int j = tid; j < nw0; j += PT_BLOCK) qnext[n - 1 - (int64_t)(s_base0 + j)] = s_win0[j];
+        }
+        {
+            uint64_t* ln = slot_line(slot);
+            block_add3<PT_BLOCK / WAVE>(my_n, my_m, 0, &ln[1], &ln[2], nullptr);
+        }
+        if (!grid_sync(ctl, G, nbar++, bar_ticks)) { fail = true; break; }
+        const int64_t nq = (int64_t)ld_dev(&slot[0]);
+        const int64_t nz = (int64_t)ld_dev(&slot[4]);
+        int64_t n_next = 0, m_next = 0;
+        for (int j = 0; j < SLOT_SPREAD; ++j) {
+            n_next += (int64_t)ld_dev(&slot[j * SLOT_LINE + 1]);
+            m_next += (int64_t)ld_dev(&slot[j * SLOT_LINE + 2]);
+        }
+        if (MODE == CLAIM_MIN) {
+            // the new vertices join visited before the next level filters on it
+            const int64_t c = (nq + G - 1) / G, cz = (nz + G - 1) / G;
+            const int64_t a0 = min(nq, (int64_t)g * c), a1 = min(nq, a0 + c);
+            const int64_t b0 = min(nz, (int64_t)g * cz), b1 = min(nz, b0 + cz);
+            for (int64_t i = a0 + tid; i < a1 + (b1 - b0); i += PT_BLOCK) {
+                const int32_t v = i < a1 ? ld_dev(&qnext[i]) : ld_dev(&qnext[n - 1 - (b0 + (i - a1))]);
+                const uint64_t bit = 1ull << (v & 63);
+                atomicOr((unsigned long long*)&visited[v >> 6], (unsigned long long)bit);
+                atomicOr((unsigned long long*)&vprev[v >> 6], (unsigned long long)bit);
+                atomicAnd((unsigned long long*)&claim[v >> 6], ~(unsigned long long)bit);
+            }
+            if (!grid_sync(ctl, G, nbar++, bar_ticks)) { fail = true; break; }
+        }
+        // the slot used two levels from now was last read before this barrier
+        if (g == 0) {
+            uint64_t* zs = ctr + (size_t)((done + 2) % SLOTS) * SLOT_WORDS;
+            for (int j = tid; j < SLOT_WORDS; j += PT_BLOCK) zs[j] = 0;
+        }
+        if (g == 0 && tid == 0 && done < rec_cap) {
+            int64_t* r = rec + done * 4;
+            r[0] = n_f;
+            r[1] = m_f;
+            r[2] = m_u;
+            r[3] = n_next;
+        }
+        found += n_next;
+        examined += m_f;
+        ++done;
+        ++level;
+        int32_t* t = qcur; qcur = qnext; qnext = t;
+        qlen = nq;
+        nz_cur = nz;
+        if (n_next == 0) { n_f = 0; m_f = 0; reason = ENG_EMPTY; break; }
+        m_u -= m_next;
+        n_f = n_next;
+        m_f = m_next;
+    }
+    if (!fail && MODE != CLAIM_MIN && done > 0) fold_vprev(qlen, nz_cur);
+    if (g == 0 && tid == 0) {
+        st->levels_done = done;
+        st->reason = fail ? ENG_TIMEOUT : reason;
+        st->found = found;
+        st->examined = examined;
+        st->qlen = qlen;
+        st->n_f = n_f;
+        st->m_f = m_f;
+        st->m_u = m_u;
+        st->level = level;
+        st->cur_is_b = (qcur == qb) ? 1 : 0;
+    }
+}
+
+template <typename OffT>
+int persist_max_groups() {
+    int dev = 0, nb = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_td_persist<OffT, CLAIM_MIN>, PT_BLOCK, 0) !=
+        hipSuccess || nb < 1)
+        return 1;
+    return nb * p.multiProcessorCount;
+}
+
+template <typename OffT>
+void launch_td_persist(const Launch& L, int mode, int groups, const OffT* off, const int32_t* cols, int32_t* parent,
+                       int32_t* depth, uint64_t* visited, uint64_t* vprev, uint64_t* claim, int32_t* qa, int32_t* qb,
+                       int64_t n, SmallIn in, SmallState* st, uint64_t* ctr, PersistCtl* ctl, int64_t* rec,
+                       int rec_cap, double alpha, int64_t edge_cap, int64_t shrink_below, int64_t max_levels) {
+    // 100 MHz device clock: 2 ms to assemble, 2 s per barrier at most
+    const long long roll_ticks = 200000, bar_ticks = 200000000;
+#define BFS_PT(M)                                                                                               \
+    hipLaunchKernelGGL((k_td_persist<OffT, M>), dim3(groups), dim3(PT_BLOCK), 0, L.stream, off, cols, parent,   \
+                       depth, visited, vprev, claim, qa, qb, n, in, st, ctr, ctl, rec, rec_cap, alpha, edge_cap, \
+                       shrink_below, max_levels, roll_ticks, bar_ticks)
+    if (mode == CLAIM_MIN) BFS_PT(CLAIM_MIN);
+    else if (mode == CLAIM_CAS) BFS_PT(CLAIM_CAS);
+    else BFS_PT(CLAIM_BITMAP);
+#undef BFS_PT
+}
+
+// frontier queue -> bitmap (words cleared first by the caller)
+__global__ void k_queue_to_bitmap(const int32_t* __restrict__ q, int64_t qlen, uint64_t* __restrict__ bits) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < qlen; i += stride) {
+        const int32_t v = q[i];
+        atomicOr((unsigned long long*)&bits[v >> 6], 1ull << (v & 63));
+    }
+}
+
+void launch_queue_to_bitmap(const Launch& L, const int32_t* q, int64_t qlen, uint64_t* bits) {
+    hipLaunchKernelGGL(k_queue_to_bitmap, dim3(grid_for(qlen, 256, L.grid_cap)), dim3(256), 0, L.stream, q, qlen,
+                       bits);
+}
+
+#define BFS_PT_INST(T)                                                                                           \
+    template int persist_max_groups<T>();                                                                        \
+    template void launch_td_persist<T>(const Launch&, int, int, const T*, const int32_t*, int32_t*, int32_t*,   \
+                                       uint64_t*, uint64_t*, uint64_t*, int32_t*, int32_t*, int64_t, SmallIn,     \
+                                       SmallState*, uint64_t*, PersistCtl*, int64_t*, int, double, int64_t,      \
+                                       int64_t, int64_t);
+BFS_PT_INST(int32_t)
+BFS_PT_INST(int64_t)
+
+}  // namespace bfsk

@@ -299,23 +299,28 @@ def test_config3_scale26_full_size(orc):
     _progress("scale 26: done")
 
 
-SMALL_CAPS = (-1, 1, 7, 100, 4096, 0, 1 << 30)
+# (small_edges, persist_edges, persist_groups): engine off, one workgroup at
+# various caps, many workgroups (including counts that do not divide the
+# frontier evenly) from the first level on, and the defaults
+ENGINE_CFGS = ((-1, 0, 0), (1, 1, 0), (7, 7, 0), (100, 100, 0), (4096, 4096, 0), (0, 0, 0),
+               (1 << 30, 1 << 30, 0), (1, 1 << 30, 2), (1, 1 << 30, 7), (1, 1 << 30, 64), (8, 200, 33))
 
 
 @pytest.mark.parametrize("name", ["grid", "path", "kron12", "er", "pieces"])
-def test_small_frontier_engine_cap_invariance(orc, graphs, name):
-    """The persistent small-frontier engine (any edge cap, or switched off with
-    a negative cap) changes neither results nor the per-level schedule and
-    counters."""
+def test_persistent_engine_invariance(orc, graphs, name):
+    """The persistent top-down engine (one workgroup, several workgroups with
+    grid barriers, any edge caps, or switched off) changes neither results
+    nor the per-level schedule and counters."""
     for off_dtype in (np.int32, np.int64):
         dg = get(graphs, name, off_dtype)
         for s in sources_for(dg.off, k=2, seed=21):
             ref = orc.bfs_min(dg.off, dg.cols, int(s))
             for dirv in (bfs.BFS_DIR_DO, bfs.BFS_DIR_TD):
                 base = None
-                for cap in SMALL_CAPS:
+                for cap, pcap, pg in ENGINE_CFGS:
                     for pm, claim in ((bfs.BFS_PARENT_MIN, 0), (bfs.BFS_PARENT_ANY, 0), (bfs.BFS_PARENT_ANY, 1)):
-                        p, d, st = dg.run(s, dir=dirv, parent_mode=pm, td_claim=claim, small_edges=cap)
+                        p, d, st = dg.run(s, dir=dirv, parent_mode=pm, td_claim=claim, small_edges=cap,
+                                          persist_edges=pcap, persist_groups=pg)
                         check(orc, dg, s, p, d, pm == bfs.BFS_PARENT_MIN, ref)
                         L = min(st.levels, bfs.STATS_MAX_LEVELS)
                         sig = (st.levels, st.reached, st.edges_examined, st.td_levels, st.bu_levels,
@@ -323,7 +328,7 @@ def test_small_frontier_engine_cap_invariance(orc, graphs, name):
                                list(st.level_mu[:L]), list(st.level_unvisited[:L]), list(st.level_examined[:L]))
                         if base is None:
                             base = sig
-                        assert sig == base, (cap, pm, claim)
+                        assert sig == base, (cap, pcap, pg, pm, claim)
 
 
 def test_grid_many_levels_closed_form(orc):
