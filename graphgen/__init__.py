@@ -36,12 +36,26 @@ class _Block(ctypes.Structure):
                 ("cp", _i64p), ("rp", _i64p)]
 
 
+_GPU_SRC = os.path.join(_HERE, "graphgen_gpu.hip")
+_GPU_LIB_PATH = os.path.join(_HERE, "libgraphgen_gpu.so")
+_gpu_lib = None
+
+
 def build(force: bool = True) -> str:
-    """Compile libgraphgen.so (gcc -O2 -fopenmp)."""
+    """Compile libgraphgen.so (gcc -O2 -fopenmp) and, where hipcc exists, the
+    GPU block generator libgraphgen_gpu.so (gfx950)."""
     tmp = _LIB_PATH + ".tmp"
     cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if os.path.exists(hipcc):
+        arch = os.environ.get("BFS_OFFLOAD_ARCH", "gfx950")
+        tmp = _GPU_LIB_PATH + ".tmp"
+        subprocess.run([hipcc, f"--offload-arch={arch}", "-O3", "-std=c++17", "-fPIC", "-shared",
+                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-o", tmp, _GPU_SRC],
+                       check=True)
+        os.replace(tmp, _GPU_LIB_PATH)
     return _LIB_PATH
 
 
@@ -213,6 +227,59 @@ def kronecker_block(scale: int, r0: int, nrows: int, c0: int, ncols: int, edgefa
     return _block_out(blk)
 
 
+def _load_gpu():
+    global _gpu_lib
+    if _gpu_lib is not None:
+        return _gpu_lib
+    if not os.path.exists(_GPU_LIB_PATH):
+        raise RuntimeError(f"{_GPU_LIB_PATH} is not built (graphgen.build())")
+    lib = ctypes.CDLL(_GPU_LIB_PATH)
+    lib.ggg_kron_block.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int64,
+                                   ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.c_void_p), _i64p, _i64p, _i64p]
+    lib.ggg_block_copy.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 6
+    lib.ggg_block_free.argtypes = [ctypes.c_void_p]
+    lib.ggg_block_free.restype = None
+    _gpu_lib = lib
+    return lib
+
+
+def kronecker_block_gpu(scale: int, r0: int, nrows: int, c0: int, ncols: int, edgefactor: int = 16,
+                        seed: int = 1, a: float = RMAT_A, b: float = RMAT_B, c: float = RMAT_C,
+                        permute: bool = True, device=None):
+    """kronecker_block built on the GPU (same draws, same arrays), returned as
+    torch tensors on `device` (default cuda:0): for blocks of graphs too large
+    to enumerate on the host."""
+    import torch
+    dev = torch.device(device or "cuda:0")
+    lib = _load_gpu()
+    h = ctypes.c_void_p()
+    nnz, nzc, nzr = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    with torch.cuda.device(dev):
+        rc = lib.ggg_kron_block(scale, edgefactor, seed, a, b, c, int(permute), r0, nrows, c0, ncols,
+                                ctypes.byref(h), ctypes.byref(nnz), ctypes.byref(nzc), ctypes.byref(nzr))
+        if rc != 0:
+            raise RuntimeError(f"ggg_kron_block failed ({rc})")
+        try:
+            out = {"nnz": nnz.value, "nzc": nzc.value, "nzr": nzr.value,
+                   "jc": torch.empty(max(nzc.value, 1), dtype=torch.int32, device=dev),
+                   "cp": torch.empty(nzc.value + 1, dtype=torch.int64, device=dev),
+                   "ir": torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev),
+                   "jr": torch.empty(max(nzr.value, 1), dtype=torch.int32, device=dev),
+                   "rp": torch.empty(nzr.value + 1, dtype=torch.int64, device=dev),
+                   "ic": torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)}
+            torch.cuda.synchronize(dev)
+            rc = lib.ggg_block_copy(h, *(out[k].data_ptr() for k in ("jc", "cp", "ir", "jr", "rp", "ic")))
+            if rc != 0:
+                raise RuntimeError(f"ggg_block_copy failed ({rc})")
+        finally:
+            lib.ggg_block_free(h)
+    for k, m in (("jc", nzc.value), ("ir", nnz.value), ("jr", nzr.value), ("ic", nnz.value)):
+        out[k] = out[k][:m]
+    return out
+
+
 def rand64(seed: int, stream: int, i: int) -> int:
     return int(_load().gg_rand64(seed, stream, i))
 
@@ -241,10 +308,11 @@ def random_sorted_subset(universe: int, k: int, seed: int) -> np.ndarray:
     if k >= universe:
         return np.arange(universe, dtype=np.int32)
     if k * 4 < universe:
-        s = set()
-        while len(s) < k:
-            s.update(rng.integers(0, universe, size=k - len(s)).tolist())
-        return np.array(sorted(s), dtype=np.int32)
+        # union of independent uniform draws, then a uniform k-subset of it
+        pool = np.unique(rng.integers(0, universe, size=k + k // 8 + 16))
+        while pool.size < k:
+            pool = np.union1d(pool, rng.integers(0, universe, size=2 * (k - pool.size) + 16))
+        return np.sort(rng.choice(pool, size=k, replace=False)).astype(np.int32)
     return np.sort(rng.choice(universe, size=k, replace=False)).astype(np.int32)
 
 

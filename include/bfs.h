@@ -96,7 +96,8 @@ typedef struct {
     int32_t parent_mode;   /* bfs_parent_mode, default BFS_PARENT_ANY             */
     double alpha;          /* top-down -> bottom-up when m_f * alpha > m_u (15)    */
     double beta;           /* bottom-up -> top-down when n_f * beta < n (18)       */
-    int32_t timing;        /* nonzero: HIP events around every kernel -> stats     */
+    int32_t timing;        /* HIP events -> stats: 0 none, 1 around every kernel,
+                              2 around the bottom-up sweeps only               */
     int32_t bu_serial;     /* entries a lane scans alone before its wave helps (0 = default) */
     int32_t grid_blocks;   /* cap on workgroups of grid-stride kernels (0 = default) */
     int32_t td_claim;      /* ANY parents, top-down claim: 0 = atomic fetch-or on a
@@ -107,10 +108,13 @@ typedef struct {
                               4096, negative = no persistent engine at all)      */
     int32_t persist_edges; /* ... and up to this many inside persist_groups
                               workgroups separated by grid barriers (0 = default
-                              262144)                                            */
-    int32_t persist_groups;/* workgroups of that engine (0 = default 256; capped
+                              65536)                                             */
+    int32_t persist_groups;/* workgroups of that engine (0 = default 64; capped
                               by what fits on the device at once)                */
-    int32_t reserved[5];
+    int32_t bu_head;       /* bottom-up, ANY parents: 0 = probe each vertex's
+                              three highest-degree neighbours first, 1 = its
+                              first three row entries (MIN always uses these)    */
+    int32_t reserved[4];
 } bfs_opts;
 
 typedef struct {

@@ -65,8 +65,10 @@ struct bfs_graph {
     // of vertices without entries, ids >= n in the last word set; their count
     uint64_t* d_iso = nullptr;
     int64_t isolated = 0;
-    // row heads for the bottom-up step: {degree, first three entries} per vertex
+    // row heads for the bottom-up step: {degree, first three entries} per
+    // vertex, and for any-parent searches {degree, three highest-degree neighbours}
     int4* d_head = nullptr;
+    int4* d_hub = nullptr;
     // workgroups of the persistent top-down engine that fit on the device
     int persist_groups_max = 1;
     // host metadata
@@ -80,21 +82,69 @@ namespace {
 // lets several threads search the same graph at once on their own streams.
 struct HostCtx {
     uint64_t* pinned = nullptr;
+    // mailbox: coherent pinned memory that kernels write directly; word 0
+    // carries the sequence number of the last completed readback
+    uint64_t* mbox = nullptr;
+    uint64_t* mbox_dev = nullptr;
+    uint64_t seq = 0;
     std::vector<hipEvent_t> events;
     ~HostCtx() {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         if (pinned) (void)hipHostFree(pinned);
+        if (mbox) (void)hipHostFree(mbox);
     }
 };
 thread_local HostCtx tl_ctx;
+constexpr int MBOX_WORDS = 511;   // data words of the 4 KiB mailbox
 
 hipError_t host_ctx(HostCtx** out) {
     if (!tl_ctx.pinned) {
         hipError_t e = hipHostMalloc((void**)&tl_ctx.pinned, 4096, hipHostMallocDefault);
         if (e != hipSuccess) { tl_ctx.pinned = nullptr; return e; }
     }
+    if (!tl_ctx.mbox) {
+        hipError_t e = hipHostMalloc((void**)&tl_ctx.mbox, 4096, hipHostMallocCoherent | hipHostMallocMapped);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&tl_ctx.mbox_dev, tl_ctx.mbox, 0);
+        if (e != hipSuccess) {
+            if (tl_ctx.mbox) (void)hipHostFree(tl_ctx.mbox);
+            tl_ctx.mbox = nullptr;
+            return e;
+        }
+        std::memset(tl_ctx.mbox, 0, 4096);
+    }
     *out = &tl_ctx;
     return hipSuccess;
+}
+
+// Wait until the mailbox shows sequence `seq`: spin (no sleep, so no wake-up
+// latency), and after 2 s ask the stream, which reports a failed launch; a
+// stream that completed without publishing is an error too.
+bfs_status mbox_wait(HostCtx* c, hipStream_t s, uint64_t seq) {
+    const auto t0 = std::chrono::steady_clock::now();
+    int polls = 0;
+    while (__atomic_load_n(&c->mbox[0], __ATOMIC_ACQUIRE) != seq) {
+        __builtin_ia32_pause();
+        if (++polls == 4096) {
+            polls = 0;
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) {
+                HIP_TRY(hipStreamSynchronize(s));
+                if (__atomic_load_n(&c->mbox[0], __ATOMIC_ACQUIRE) != seq)
+                    return fail(BFS_E_HIP, "readback did not arrive");
+            }
+        }
+    }
+    return BFS_OK;
+}
+
+// nw (<= MBOX_WORDS) words of device memory, read after all earlier work on s
+bfs_status readback(HostCtx* c, hipStream_t s, const void* src, int nw, const uint64_t** out) {
+    if (nw < 0 || nw > MBOX_WORDS) return fail(BFS_E_INVALID_ARG, "readback of %d words", nw);
+    const uint64_t seq = ++c->seq;
+    launch_post(s, (const uint64_t*)src, nw, c->mbox_dev, seq);
+    HIP_TRY(hipGetLastError());
+    bfs_status st = mbox_wait(c, s, seq);
+    *out = c->mbox + 1;
+    return st;
 }
 
 // -------------------------------------------------------------- workspace layout
@@ -214,7 +264,7 @@ size_t multi_bytes(const bfs_graph* g, int) { return multi_layout(g).total; }
 struct Timer {
     HostCtx* g;
     hipStream_t s;
-    bool on;
+    int mode;   // bfs_opts.timing: 0 off, 1 every kernel, 2 the bottom-up sweep only
     struct Rec { int kind; int level; size_t ev; };
     std::vector<Rec> recs;
     size_t used = 0;
@@ -228,8 +278,11 @@ struct Timer {
         }
         return hipSuccess;
     }
+    bool on = false;   // the bracket being recorded
+    bool wants(int kind) const { return mode == 1 || (mode == 2 && kind == BFS_K_BU_SWEEP); }
     // brackets one launch (or a few launches of one kind)
-    hipError_t begin() {
+    hipError_t begin(int kind) {
+        on = wants(kind);
         if (!on) return hipSuccess;
         hipError_t r = ensure(used + 2);
         if (r != hipSuccess) return r;
@@ -237,6 +290,7 @@ struct Timer {
     }
     hipError_t end(int kind, int level) {
         if (!on) return hipSuccess;
+        on = false;
         hipError_t r = hipEventRecord(g->events[used + 1], s);
         recs.push_back({kind, level, used});
         used += 2;
@@ -282,17 +336,20 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     Launch L{stream, o.grid_blocks > 0 ? o.grid_blocks : 2048};
     HostCtx* ctx = nullptr;
     HIP_TRY(host_ctx(&ctx));
-    Timer T{ctx, stream, o.timing != 0, {}, 0};
+    Timer T{ctx, stream, o.timing, {}, 0};
 
     // degree of the source: the first frontier's edge count
-    uint64_t* h = ctx->pinned;
-    OffT* hoff = (OffT*)h;
-    HIP_TRY(hipMemcpyAsync(hoff, (const char*)g->off + sizeof(OffT) * src, 2 * sizeof(OffT), hipMemcpyDeviceToHost,
-                           stream));
-    HIP_TRY(hipStreamSynchronize(stream));
-    const int64_t deg_s = (int64_t)hoff[1] - (int64_t)hoff[0];
+    const uint64_t* h = nullptr;   // the last level's counters, in the mailbox
+    {
+        const uint64_t seq = ++ctx->seq;
+        launch_post_row<OffT>(stream, off, src, ctx->mbox_dev, seq);
+        HIP_TRY(hipGetLastError());
+        bfs_status ws_ = mbox_wait(ctx, stream, seq);
+        if (ws_ != BFS_OK) return ws_;
+    }
+    const int64_t deg_s = (int64_t)ctx->mbox[2] - (int64_t)ctx->mbox[1];
 
-    HIP_TRY(T.begin());
+    HIP_TRY(T.begin(BFS_K_INIT));
     launch_init(L, parent, depth, n, visited, vprev, fbits, claim, g->d_iso, W, qcur, src, counters,
                 (int64_t)((Lo.ctl_end - Lo.counters) / sizeof(uint64_t)));
     HIP_TRY(hipGetLastError());
@@ -334,7 +391,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             const int rec_cap = (st && level < BFS_STATS_MAX_LEVELS) ? BFS_STATS_MAX_LEVELS - level : 0;
             // forced top-down never switches: with alpha = 0 the rule m_f * alpha > m_u cannot fire
             const double eng_alpha = o.dir == BFS_DIR_TD ? 0.0 : o.alpha;
-            HIP_TRY(T.begin());
+            HIP_TRY(T.begin(BFS_K_TD_EXPAND));
             launch_td_persist<OffT>(L, claim_mode, groups, off, g->cols, parent, depth, visited, vprev, claim, qcur,
                                     qnext, n, in, d_small, (uint64_t*)(ws + Lo.pctr), (PersistCtl*)(ws + Lo.pctl),
                                     d_rec, rec_cap, eng_alpha, multi ? cap_multi : cap_one, multi ? cap_one / 2 : 0,
@@ -344,14 +401,17 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             // state and level records in one copy, then the whole control
             // block is cleared: the level counters (the level index moved on),
             // the engine's barrier words and its state (reason 0 = not run)
-            HIP_TRY(hipMemcpyAsync(h, d_small, (Lo.rec - Lo.small) + sizeof(int64_t) * 4 * (size_t)rec_cap,
-                                   hipMemcpyDeviceToHost, stream));
+            const uint64_t* hb = nullptr;
+            {
+                const int nw = (int)(((Lo.rec - Lo.small) + sizeof(int64_t) * 4 * (size_t)rec_cap) / sizeof(uint64_t));
+                bfs_status rs = readback(ctx, stream, d_small, nw, &hb);
+                if (rs != BFS_OK) return rs;
+            }
             launch_clear_words(L, counters, (int64_t)((Lo.ctl_end - Lo.counters) / sizeof(uint64_t)));
             HIP_TRY(hipGetLastError());
-            HIP_TRY(hipStreamSynchronize(stream));
             SmallState hs;
-            std::memcpy(&hs, h, sizeof(hs));
-            const int64_t* recs = (const int64_t*)((const char*)h + (Lo.rec - Lo.small));
+            std::memcpy(&hs, hb, sizeof(hs));
+            const int64_t* recs = (const int64_t*)((const char*)hb + (Lo.rec - Lo.small));
             if (st) st->launches[BFS_K_TD_EXPAND] += 1;
             if (hs.reason == ENG_NOT_RUN) {
                 // the workgroups could not all be resident at once (a busy
@@ -395,7 +455,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
         if (cur_dir == 0 && !fmt_queue) {
             // bottom-up -> top-down: the frontier bitmap becomes a queue; its
             // length stays on the device (slot word 4, cleared with the slot)
-            HIP_TRY(T.begin());
+            HIP_TRY(T.begin(BFS_K_CONVERT));
             launch_bitmap_to_queue(L, fbits, W, qcur, slot + 4);
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_CONVERT, level));
@@ -408,16 +468,16 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
         const int32_t next_depth = level + 1;
         if (cur_dir == 0) {
             if (m_f > 0) {
-                HIP_TRY(T.begin());
+                HIP_TRY(T.begin(BFS_K_TD_SCAN));
                 int nl = launch_td_scan<OffT>(L, off, qcur, qlen_dev, qlen, scan, tiles, partial, nullptr);
                 HIP_TRY(hipGetLastError());
                 HIP_TRY(T.end(BFS_K_TD_SCAN, level));
-                HIP_TRY(T.begin());
+                HIP_TRY(T.begin(BFS_K_TD_EXPAND));
                 launch_td_expand<OffT>(L, claim_mode, off, g->cols, g->nnz, qcur, qlen_dev, qlen, scan, tiles, m_f,
                                        parent, depth, visited, claim, qnext, slot, zslot, next_depth);
                 HIP_TRY(hipGetLastError());
                 HIP_TRY(T.end(BFS_K_TD_EXPAND, level));
-                HIP_TRY(T.begin());
+                HIP_TRY(T.begin(BFS_K_CONVERT));
                 fbits_stale = false;
                 launch_merge(L, claim_mode == CLAIM_MIN, visited, vprev, claim, fbits, W);
                 HIP_TRY(hipGetLastError());
@@ -432,7 +492,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             // previous level (or by init) and reads as an empty next frontier
         } else {
             if (fbits_stale) {
-                HIP_TRY(T.begin());
+                HIP_TRY(T.begin(BFS_K_CONVERT));
                 launch_clear_words(L, fbits, W);
                 launch_queue_to_bitmap(L, qcur, qlen, fbits);
                 HIP_TRY(hipGetLastError());
@@ -441,15 +501,19 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                 fbits_stale = false;
             }
             fmt_queue = false;
-            HIP_TRY(T.begin());
-            launch_bu_sweep<OffT>(L, g->d_head, off, g->cols, fbits, nbits, visited, vprev, parent, depth, W,
-                                  next_depth, serial, slot, zslot);
+            HIP_TRY(T.begin(BFS_K_BU_SWEEP));
+            // any-parent searches probe the highest-degree neighbours first
+            const bool hub = claim_mode != CLAIM_MIN && o.bu_head == 0;
+            launch_bu_sweep<OffT>(L, hub ? g->d_hub : g->d_head, hub, off, g->cols, fbits, nbits, visited, vprev,
+                                  parent, depth, W, next_depth, serial, slot, zslot);
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_BU_SWEEP, level));
             if (st) st->launches[BFS_K_BU_SWEEP] += 1;
         }
-        HIP_TRY(hipMemcpyAsync(h, slot, sizeof(uint64_t) * SLOT_WORDS, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
+        {
+            bfs_status rs = readback(ctx, stream, slot, SLOT_WORDS, &h);
+            if (rs != BFS_OK) return rs;
+        }
         const int64_t n_next = (int64_t)slot_sum(h, S_NNEXT);
         const int64_t m_next = (int64_t)slot_sum(h, S_MNEXT);
         const int64_t lvl_examined = cur_dir == 0 ? m_f : (int64_t)slot_sum(h, S_EXAMINED);
@@ -486,7 +550,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
         st->reached = reached;
         st->isolated = g->isolated;
         st->edges_examined = examined;
-        if (T.on) {
+        if (T.mode) {
             HIP_TRY(hipStreamSynchronize(stream));
             T.collect(st);
         }
@@ -519,19 +583,22 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
     Launch L{stream, o.grid_blocks > 0 ? o.grid_blocks : 2048};
     HostCtx* ctx = nullptr;
     HIP_TRY(host_ctx(&ctx));
-    Timer T{ctx, stream, o.timing != 0, {}, 0};
-    uint64_t* h = ctx->pinned;
+    Timer T{ctx, stream, o.timing, {}, 0};
+    uint64_t* hp = ctx->pinned;
+    const uint64_t* h = nullptr;   // counters of the last readback, in the mailbox
 
     // sources travel through the pinned buffer (k <= 64 ids)
-    std::memcpy(h, h_src, sizeof(int64_t) * (size_t)k);
-    HIP_TRY(hipMemcpyAsync(d_src, h, sizeof(int64_t) * (size_t)k, hipMemcpyHostToDevice, stream));
+    std::memcpy(hp, h_src, sizeof(int64_t) * (size_t)k);
+    HIP_TRY(hipMemcpyAsync(d_src, hp, sizeof(int64_t) * (size_t)k, hipMemcpyHostToDevice, stream));
     uint64_t* slot_init = counters + (size_t)(SLOTS - 1) * SLOT_WORDS;   // "level -1"
-    HIP_TRY(T.begin());
+    HIP_TRY(T.begin(BFS_K_INIT));
     launch_ms_init<OffT>(L, off, n, k, d_src, g->d_iso, visited, F, N, par_vm, lvl_vm, qa, counters, slot_init);
     HIP_TRY(hipGetLastError());
     HIP_TRY(T.end(BFS_K_INIT, -1));
-    HIP_TRY(hipMemcpyAsync(h, slot_init, sizeof(uint64_t) * SLOT_WORDS, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
+    {
+        bfs_status rs = readback(ctx, stream, slot_init, SLOT_WORDS, &h);
+        if (rs != BFS_OK) return rs;
+    }
     if (st) st->launches[BFS_K_INIT] += 2;
 
     int64_t n_f = (int64_t)slot_sum(h, M_SLOT_NNEXT), m_f = (int64_t)slot_sum(h, M_SLOT_MNEXT);
@@ -554,7 +621,7 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
         uint64_t* pslot = counters + (size_t)((level + SLOTS - 1) % SLOTS) * SLOT_WORDS;
         const uint16_t next_level = (uint16_t)(level + 1);
         if (cur_dir == 0) {
-            HIP_TRY(T.begin());
+            HIP_TRY(T.begin(BFS_K_CONVERT));
             int conv = 0;
             if (!fq_valid) {
                 launch_ms_mask_to_queue(L, F, n, qa, slot + M_SLOT_CONV);
@@ -566,7 +633,7 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
             else if (n_dirty == 1 && nd_len > 0) { launch_ms_clear_queue(L, qb, nullptr, nd_len, N); ++conv; }
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_CONVERT, level));
-            HIP_TRY(T.begin());
+            HIP_TRY(T.begin(BFS_K_MS_LEVEL));
             if (m_f > 0)
                 launch_ms_td<OffT>(L, off, g->cols, g->nnz, qa, qlen, m_f, scan, tiles, partial, F, N, visited, full,
                                    qb, par_vm, lvl_vm, next_level, serial, slot, zslot);
@@ -574,15 +641,17 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
             HIP_TRY(T.end(BFS_K_MS_LEVEL, level));
             if (st) { st->launches[BFS_K_CONVERT] += conv; st->launches[BFS_K_MS_LEVEL] += m_f > 0 ? 3 : 0; }
         } else {
-            HIP_TRY(T.begin());
+            HIP_TRY(T.begin(BFS_K_MS_LEVEL));
             launch_ms_bu<OffT>(L, off, g->cols, n, F, N, visited, full, pslot + M_SLOT_OR, par_vm, lvl_vm,
                                next_level, serial, slot, zslot);
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_MS_LEVEL, level));
             if (st) st->launches[BFS_K_MS_LEVEL] += 1;
         }
-        HIP_TRY(hipMemcpyAsync(h, slot, sizeof(uint64_t) * SLOT_WORDS, hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
+        {
+            bfs_status rs = readback(ctx, stream, slot, SLOT_WORDS, &h);
+            if (rs != BFS_OK) return rs;
+        }
         const int64_t n_next = (int64_t)slot_sum(h, M_SLOT_NNEXT), m_next = (int64_t)slot_sum(h, M_SLOT_MNEXT);
         const int64_t lvl_exam = cur_dir == 0 ? m_f + (int64_t)slot_sum(h, M_SLOT_EXAM) : (int64_t)slot_sum(h, M_SLOT_EXAM);
         examined += lvl_exam;
@@ -620,7 +689,7 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
         n_f = n_next;
         m_f = m_next;
     }
-    HIP_TRY(T.begin());
+    HIP_TRY(T.begin(BFS_K_MS_OUTPUT));
     launch_ms_output(L, n, k, d_src, visited, g->d_iso, par_vm, lvl_vm, parent, depth);
     HIP_TRY(hipGetLastError());
     HIP_TRY(T.end(BFS_K_MS_OUTPUT, -1));
@@ -631,7 +700,7 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
         st->reached = reached_pairs;
         st->isolated = g->isolated;
         st->edges_examined = examined;
-        if (T.on) T.collect(st);
+        if (T.mode) T.collect(st);
         st->total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     }
     return BFS_OK;
@@ -651,6 +720,9 @@ bfs_status build_derived(bfs_graph* g, hipStream_t s) {
     g->isolated = (int64_t)g->h_buf[0];
     HIP_TRY(hipMalloc((void**)&g->d_head, sizeof(int4) * (size_t)g->n));
     launch_row_heads<OffT>(L, (const OffT*)g->off, g->cols, g->n, g->d_head);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMalloc((void**)&g->d_hub, sizeof(int4) * (size_t)g->n));
+    launch_hub_heads<OffT>(L, (const OffT*)g->off, g->cols, g->d_head, g->n, g->d_hub);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     return BFS_OK;
@@ -831,6 +903,7 @@ void bfs_destroy_graph(bfs_graph* g) {
     if (!g) return;
     if (g->d_iso) (void)hipFree(g->d_iso);
     if (g->d_head) (void)hipFree(g->d_head);
+    if (g->d_hub) (void)hipFree(g->d_hub);
     if (g->h_buf) (void)hipHostFree(g->h_buf);
     delete g;
 }

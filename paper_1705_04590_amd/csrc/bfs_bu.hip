@@ -42,7 +42,13 @@ __device__ __forceinline__ bool bit_of(uint64_t word, int32_t c) { return (word 
 
 __device__ __forceinline__ uint64_t stream_load(const uint64_t* p) { return __builtin_nontemporal_load(p); }
 
-template <typename OffT>
+// HUB = 0: `head` holds each row's first three entries (row order, as the
+// minimum-id parent needs).  HUB = 1 (any-parent searches): it holds the three
+// neighbours of highest degree; a vertex of a large bottom-up level finds its
+// frontier among them far more often (the frontier of that level is made of
+// high-degree vertices), so fewer probes are made; a miss then scans the whole
+// row from its start.
+template <typename OffT, int HUB>
 __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
     const int4* __restrict__ head, const OffT* __restrict__ off, const int32_t* __restrict__ cols,
     const uint64_t* __restrict__ fbits, uint64_t* __restrict__ nbits, uint64_t* __restrict__ visited,
@@ -110,14 +116,16 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
                 if (deg > 0 && bit_of(fbits[h.y >> 6], h.y)) { par = h.y; pos = 0; }
                 else if (deg > 1 && bit_of(fbits[h.z >> 6], h.z)) { par = h.z; pos = 1; }
                 else if (deg > 2 && bit_of(fbits[h.w >> 6], h.w)) { par = h.w; pos = 2; }
-                // continuation: positions relative to the row start (rows hold < 2^31 entries)
+                // continuation: positions relative to the row start (rows hold < 2^31 entries);
+                // `pos` counts the head probes too when the head is not a row prefix
+                constexpr int32_t skip = HUB ? 0 : 3, pbase = HUB ? 3 : 0;
                 int64_t beg = 0;
                 int32_t rp = deg;   // next entry to scan; deg when nothing is left
                 if (par < 0 && deg > 3) {
                     beg = (int64_t)off[v];
-                    const int32_t lim = deg - 3 > serial_len ? 3 + serial_len : deg;
+                    const int32_t lim = deg - skip > serial_len ? skip + serial_len : deg;
                     const int32_t* row = cols + beg;
-                    for (rp = 3; rp < lim; rp += 4) {
+                    for (rp = skip; rp < lim; rp += 4) {
                         // four entries at once: loads first, then probes
                         const int32_t c0 = row[rp];
                         const int32_t c1 = rp + 1 < lim ? row[rp + 1] : -1;
@@ -132,7 +140,7 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
                         if (c2 >= 0 && bit_of(f2, c2)) { par = c2; rp += 2; break; }
                         if (c3 >= 0 && bit_of(f3, c3)) { par = c3; rp += 3; break; }
                     }
-                    if (par >= 0) pos = rp;
+                    if (par >= 0) pos = pbase + rp;
                     else if (rp > lim) rp = lim;
                 }
                 uint64_t rem = __ballot(par < 0 && rp < deg);
@@ -161,11 +169,11 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
                     }
                     if (lane == l) {
                         par = got;
-                        if (got >= 0) pos = gotpos;
+                        if (got >= 0) pos = pbase + gotpos;
                     }
                 }
                 if (par >= 0) found(v, par, pos, deg);
-                else if (act) my_x += (uint64_t)deg;
+                else if (act) my_x += (uint64_t)(deg > 3 ? pbase + deg : deg);
             }
             wave_lds_sync();
         }
@@ -192,14 +200,18 @@ static int group_words(int64_t W, int waves) {
 }
 
 template <typename OffT>
-void launch_bu_sweep(const Launch& L, const int4* head, const OffT* off, const int32_t* cols, const uint64_t* fbits,
-                     uint64_t* nbits, uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W,
-                     int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot) {
+void launch_bu_sweep(const Launch& L, const int4* head, bool hub, const OffT* off, const int32_t* cols,
+                     const uint64_t* fbits, uint64_t* nbits, uint64_t* visited, uint64_t* vprev, int32_t* parent,
+                     int32_t* depth, int64_t W, int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot) {
     const int gw = group_words(W, L.grid_cap * (BU_BLOCK / WAVE));
     const int64_t G = (W + gw - 1) / gw;
     const int g = grid_for(G, BU_BLOCK / WAVE, L.grid_cap);
-    hipLaunchKernelGGL(k_bu_sweep<OffT>, dim3(g), dim3(BU_BLOCK), 0, L.stream, head, off, cols, fbits, nbits,
-                       visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot, zslot);
+    if (hub)
+        hipLaunchKernelGGL((k_bu_sweep<OffT, 1>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, off, cols, fbits, nbits,
+                           visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot, zslot);
+    else
+        hipLaunchKernelGGL((k_bu_sweep<OffT, 0>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, off, cols, fbits, nbits,
+                           visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot, zslot);
 }
 
 // ------------------------------------------------------------------ row heads
@@ -225,11 +237,51 @@ void launch_row_heads(const Launch& L, const OffT* off, const int32_t* cols, int
                        head);
 }
 
+// hub heads: {deg, the three neighbours of highest degree (ties: smaller id)}
+// chosen among the first HUB_SCAN entries of the row; degrees come from the
+// row heads
+constexpr int HUB_SCAN = 64;
+
+__device__ __forceinline__ bool hub_before(int32_t da, int32_t a, int32_t db, int32_t b) {
+    return da > db || (da == db && a < b);
+}
+
+template <typename OffT>
+__global__ void k_hub_heads(const OffT* __restrict__ off, const int32_t* __restrict__ cols,
+                            const int4* __restrict__ head, int64_t n, int4* __restrict__ hub) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const int64_t b = (int64_t)off[v];
+        const int64_t d = (int64_t)off[v + 1] - b;
+        const int64_t m = d < HUB_SCAN ? d : HUB_SCAN;
+        int32_t c0 = -1, c1 = -1, c2 = -1, d0 = -1, d1 = -1, d2 = -1;
+        for (int64_t i = 0; i < m; ++i) {
+            const int32_t c = cols[b + i];
+            const int32_t dc = head[c].x;
+            if (hub_before(dc, c, d0, c0) || c0 < 0) {
+                c2 = c1; d2 = d1; c1 = c0; d1 = d0; c0 = c; d0 = dc;
+            } else if (hub_before(dc, c, d1, c1) || c1 < 0) {
+                c2 = c1; d2 = d1; c1 = c; d1 = dc;
+            } else if (hub_before(dc, c, d2, c2) || c2 < 0) {
+                c2 = c; d2 = dc;
+            }
+        }
+        hub[v] = make_int4((int32_t)d, c0, c1, c2);
+    }
+}
+
+template <typename OffT>
+void launch_hub_heads(const Launch& L, const OffT* off, const int32_t* cols, const int4* head, int64_t n, int4* hub) {
+    hipLaunchKernelGGL(k_hub_heads<OffT>, dim3(grid_for(n, 256, L.grid_cap)), dim3(256), 0, L.stream, off, cols, head,
+                       n, hub);
+}
+
 #define BFS_BU_INST(T)                                                                                           \
-    template void launch_bu_sweep<T>(const Launch&, const int4*, const T*, const int32_t*, const uint64_t*,      \
-                                     uint64_t*, uint64_t*, uint64_t*, int32_t*, int32_t*, int64_t, int32_t, int, \
-                                     uint64_t*, uint64_t*);                                                      \
-    template void launch_row_heads<T>(const Launch&, const T*, const int32_t*, int64_t, int4*);
+    template void launch_bu_sweep<T>(const Launch&, const int4*, bool, const T*, const int32_t*,               \
+                                     const uint64_t*, uint64_t*, uint64_t*, uint64_t*, int32_t*, int32_t*,      \
+                                     int64_t, int32_t, int, uint64_t*, uint64_t*);                               \
+    template void launch_row_heads<T>(const Launch&, const T*, const int32_t*, int64_t, int4*);                 \
+    template void launch_hub_heads<T>(const Launch&, const T*, const int32_t*, const int4*, int64_t, int4*);
 BFS_BU_INST(int32_t)
 BFS_BU_INST(int64_t)
 

@@ -76,14 +76,22 @@ void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t*
                       int32_t next_depth);
 
 template <typename OffT>
-void launch_bu_sweep(const Launch& L, const int4* head, const OffT* off, const int32_t* cols, const uint64_t* fbits,
-                     uint64_t* nbits, uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W,
-                     int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot);
+void launch_bu_sweep(const Launch& L, const int4* head, bool hub, const OffT* off, const int32_t* cols,
+                     const uint64_t* fbits, uint64_t* nbits, uint64_t* visited, uint64_t* vprev, int32_t* parent,
+                     int32_t* depth, int64_t W, int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot);
 // per-vertex row heads {degree, first three entries (-1 when absent)}
 template <typename OffT>
 void launch_row_heads(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, int4* head);
+// per-vertex hub heads {degree, three highest-degree neighbours (-1 when absent)}
+template <typename OffT>
+void launch_hub_heads(const Launch& L, const OffT* off, const int32_t* cols, const int4* head, int64_t n, int4* hub);
 
 void launch_clear_words(const Launch& L, uint64_t* w, int64_t nw);
+// host mailbox: dst[1..nw] = src[0..nw), then dst[0] = seq (dst: coherent pinned host memory)
+void launch_post(hipStream_t s, const uint64_t* src, int nw, uint64_t* dst, uint64_t seq);
+// host mailbox: dst[1] = off[v], dst[2] = off[v+1], then dst[0] = seq
+template <typename OffT>
+void launch_post_row(hipStream_t s, const OffT* off, int64_t v, uint64_t* dst, uint64_t seq);
 void launch_queue_to_bitmap(const Launch& L, const int32_t* q, int64_t qlen, uint64_t* bits);
 
 // persistent top-down engine state (device memory, read and written by the engine)

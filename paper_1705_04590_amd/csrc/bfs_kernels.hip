@@ -94,6 +94,36 @@ void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, ui
                        W, queue, src, counters, counter_words);
 }
 
+// ------------------------------------------------------------------ host mailbox
+// Copies nw words to a coherent pinned host buffer and then publishes `seq`
+// in its word 0 (system-scope release after a system-scope fence), so the
+// host can spin on word 0 instead of sleeping in a stream synchronisation.
+__global__ void k_post(const uint64_t* __restrict__ src, int nw, uint64_t* dst, uint64_t seq) {
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[1 + i] = src[i];
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(&dst[0], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+template <typename OffT>
+__global__ void k_post_row(const OffT* __restrict__ off, int64_t v, uint64_t* dst, uint64_t seq) {
+    dst[1] = (uint64_t)(int64_t)off[v];
+    dst[2] = (uint64_t)(int64_t)off[v + 1];
+    __threadfence_system();
+    __hip_atomic_store(&dst[0], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+void launch_post(hipStream_t s, const uint64_t* src, int nw, uint64_t* dst, uint64_t seq) {
+    hipLaunchKernelGGL(k_post, dim3(1), dim3(256), 0, s, src, nw, dst, seq);
+}
+
+template <typename OffT>
+void launch_post_row(hipStream_t s, const OffT* off, int64_t v, uint64_t* dst, uint64_t seq) {
+    hipLaunchKernelGGL(k_post_row<OffT>, dim3(1), dim3(1), 0, s, off, v, dst, seq);
+}
+template void launch_post_row<int32_t>(hipStream_t, const int32_t*, int64_t, uint64_t*, uint64_t);
+template void launch_post_row<int64_t>(hipStream_t, const int64_t*, int64_t, uint64_t*, uint64_t);
+
 // ------------------------------------------------------------------ frontier degree scan
 template <typename OffT>
 int launch_td_scan(const Launch& L, const OffT* off, const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host,

@@ -25,7 +25,8 @@ def test_autotune_single_and_multi_are_result_invariant(orc, tmp_path):
     cache = str(tmp_path / "tune.json")
     r1 = autotune.tune(g, tune_src, k=1, cache_path=cache)
     assert r1["trials"] > 10 and r1["tuned_ms"] <= r1["default_ms"] * 1.0001
-    assert autotune.tune(g, tune_src, k=1, cache_path=cache) == r1   # served from the cache
+    again = autotune.tune(g, tune_src, k=1, cache_path=cache)   # served from the cache
+    assert again.pop("cached") is True and again == r1
     ws = bfs.workspace(g, 1, DEV)
     par = torch.empty(n, dtype=torch.int32, device=DEV)
     dep = torch.empty(n, dtype=torch.int32, device=DEV)
