@@ -157,6 +157,8 @@ def serve_bench(args):
         srv.bfs_server_drain()
         st = srv.bfs_server_stats_get()
         srv.bfs_server_destroy()
+        free, total = torch.cuda.mem_get_info()
+        log(f"[serve]   server done: {free / 2**30:.1f} of {total / 2**30:.1f} GiB free")
         return st
 
     m = args.serve_requests

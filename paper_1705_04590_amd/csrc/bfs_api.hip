@@ -183,7 +183,7 @@ SingleLayout single_layout(const bfs_graph* g) {
 }
 
 struct BlockLayout {
-    size_t header, q, scan, tiles, partial, spa, occ, bpar, bmask, total;
+    size_t header, q, scan, tiles, partial, spa, occ, fmark, bpar, bmask, total;
 };
 
 BlockLayout block_layout(const bfs_graph* g) {
@@ -202,6 +202,7 @@ BlockLayout block_layout(const bfs_graph* g) {
     L.partial = o; o = align_up(o + sizeof(int64_t) * (size_t)((scan_len + SCAN_TILE - 1) / SCAN_TILE + 2));
     L.spa = o; o = align_up(o + sizeof(uint32_t) * (size_t)g->nrows);
     L.occ = o; o = align_up(o + sizeof(uint64_t) * (size_t)wr);
+    L.fmark = o; o = align_up(o + sizeof(uint64_t) * (size_t)((g->ncols + 63) / 64 + 1));
     L.bpar = o; o = align_up(o + sizeof(int32_t) * (size_t)(chunks * 64 + 1));
     L.bmask = o; o = align_up(o + sizeof(uint64_t) * (size_t)(chunks + 1));
     L.total = o;
@@ -221,6 +222,7 @@ BlockWs block_ws(const bfs_graph* g, char* ws) {
     W.partial = (int64_t*)(ws + Lo.partial);
     W.spa = (uint32_t*)(ws + Lo.spa);
     W.occ = (uint64_t*)(ws + Lo.occ);
+    W.fmark = (uint64_t*)(ws + Lo.fmark);
     W.bpar = (int32_t*)(ws + Lo.bpar);
     W.bmask = (uint64_t*)(ws + Lo.bmask);
     return W;
@@ -235,7 +237,7 @@ BlockArgs block_args(const bfs_graph* g) {
 }
 
 struct MultiLayout {
-    size_t counters, src, visited, F, N, qa, qb, scan, tiles, partial, par, lvl, total;
+    size_t counters, src, visited, F, N, hubmark, qa, qb, scan, tiles, partial, par, lvl, total;
 };
 
 MultiLayout multi_layout(const bfs_graph* g) {
@@ -247,6 +249,7 @@ MultiLayout multi_layout(const bfs_graph* g) {
     L.visited = o; o = align_up(o + sizeof(uint64_t) * (size_t)n);
     L.F = o; o = align_up(o + sizeof(uint64_t) * (size_t)n);
     L.N = o; o = align_up(o + sizeof(uint64_t) * (size_t)n);
+    L.hubmark = o; o = align_up(o + sizeof(uint64_t) * (size_t)((n + 63) / 64 + 1));
     L.qa = o; o = align_up(o + sizeof(int32_t) * (size_t)(n + 1));
     L.qb = o; o = align_up(o + sizeof(int32_t) * (size_t)(n + 1));
     L.scan = o; o = align_up(o + sizeof(int64_t) * (size_t)(n + 2));
@@ -407,10 +410,14 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                 bfs_status rs = readback(ctx, stream, d_small, nw, &hb);
                 if (rs != BFS_OK) return rs;
             }
-            launch_clear_words(L, counters, (int64_t)((Lo.ctl_end - Lo.counters) / sizeof(uint64_t)));
-            HIP_TRY(hipGetLastError());
             SmallState hs;
             std::memcpy(&hs, hb, sizeof(hs));
+            // a search that goes on needs the control block cleared (level
+            // counters: the level index moved on; barrier words; state)
+            if (hs.reason != ENG_EMPTY) {
+                launch_clear_words(L, counters, (int64_t)((Lo.ctl_end - Lo.counters) / sizeof(uint64_t)));
+                HIP_TRY(hipGetLastError());
+            }
             const int64_t* recs = (const int64_t*)((const char*)hb + (Lo.rec - Lo.small));
             if (st) st->launches[BFS_K_TD_EXPAND] += 1;
             if (hs.reason == ENG_NOT_RUN) {
@@ -571,6 +578,7 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
     uint64_t* visited = (uint64_t*)(ws + Lo.visited);
     uint64_t* F = (uint64_t*)(ws + Lo.F);
     uint64_t* N = (uint64_t*)(ws + Lo.N);
+    uint64_t* hubmark = (uint64_t*)(ws + Lo.hubmark);
     int32_t* qa = (int32_t*)(ws + Lo.qa);
     int32_t* qb = (int32_t*)(ws + Lo.qb);
     int64_t* scan = (int64_t*)(ws + Lo.scan);
@@ -593,6 +601,7 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
     uint64_t* slot_init = counters + (size_t)(SLOTS - 1) * SLOT_WORDS;   // "level -1"
     HIP_TRY(T.begin(BFS_K_INIT));
     launch_ms_init<OffT>(L, off, n, k, d_src, g->d_iso, visited, F, N, par_vm, lvl_vm, qa, counters, slot_init);
+    launch_clear_words(L, hubmark, (n + 63) / 64 + 1);
     HIP_TRY(hipGetLastError());
     HIP_TRY(T.end(BFS_K_INIT, -1));
     {
@@ -636,7 +645,7 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
             HIP_TRY(T.begin(BFS_K_MS_LEVEL));
             if (m_f > 0)
                 launch_ms_td<OffT>(L, off, g->cols, g->nnz, qa, qlen, m_f, scan, tiles, partial, F, N, visited, full,
-                                   qb, par_vm, lvl_vm, next_level, serial, slot, zslot);
+                                   qb, par_vm, lvl_vm, next_level, serial, hubmark, slot, zslot);
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_MS_LEVEL, level));
             if (st) { st->launches[BFS_K_CONVERT] += conv; st->launches[BFS_K_MS_LEVEL] += m_f > 0 ? 3 : 0; }
@@ -732,6 +741,7 @@ bfs_status build_derived(bfs_graph* g, hipStream_t s) {
 
 namespace bfsk {
 int64_t graph_vertices(const bfs_graph* g) { return (g && g->kind == KIND_CSR) ? g->n : 0; }
+void set_last_error(const char* msg) { g_err = msg ? msg : ""; }
 }  // namespace bfsk
 
 // ================================================================== C ABI

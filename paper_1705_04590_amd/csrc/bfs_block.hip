@@ -4,8 +4,9 @@
 // Top-down (Alg. 3, the sparse-matrix sparse-vector product on the
 // (select2nd, min) semiring of Section 4.2, with a sparse accumulator as in
 // Section 5.2):
-//   1. every frontier column is looked up in JC (binary search); the JC
-//      indices found are compacted into a queue
+//   1. every frontier column is looked up in JC (binary search; for dense
+//      frontiers one pass over JC against a column bitmap of F instead); the
+//      JC indices found are compacted into a queue
 //   2. a prefix sum over their column lengths splits all their entries into
 //      fixed tiles (the same edge-balanced tiling as the whole-graph
 //      top-down step)
@@ -26,6 +27,8 @@
 //      pairs in ascending row order.
 // Both paths run entirely on the device: lengths and totals never travel to
 // the host, so the calls are asynchronous on their stream.
+#include <cmath>
+
 #include "bfs_device.h"
 
 namespace bfsk {
@@ -257,11 +260,50 @@ struct ChunkEmit {
     __device__ void last(int64_t, int64_t total) const { *nout = total; }
 };
 
+// Dense frontiers: when |F| binary searches would cost more than one pass
+// over JC (|F| log2 nzc > nzc), F is marked in a column bitmap and JC is
+// scanned once; the found JC indices come out of an ordered compaction.
+__global__ void k_blk_mark(const int32_t* __restrict__ F, int64_t nf, uint64_t* __restrict__ fmark, int clear) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += stride) {
+        const int32_t c = F[i];
+        if (clear) fmark[c >> 6] = 0;
+        else atomicOr((unsigned long long*)&fmark[c >> 6], 1ull << (c & 63));
+    }
+}
+
+struct JcInFrontier {
+    const int32_t* jc;
+    const uint64_t* fmark;
+    __device__ int64_t operator()(int64_t i) const {
+        const int32_t c = jc[i];
+        return (int64_t)((fmark[c >> 6] >> (c & 63)) & 1ull);
+    }
+};
+
+struct JcIndexSink {
+    int32_t* q;
+    uint64_t* qlen;
+    __device__ void item(int64_t i, int64_t before, int64_t d) const {
+        if (d) q[before] = (int32_t)i;
+    }
+    __device__ void last(int64_t, int64_t total) const { *qlen = (uint64_t)total; }
+};
+
 // ---------------------------------------------------------------- launchers
 void launch_block_td(const Launch& L, const BlockArgs& B, const int32_t* F, int64_t nf, int32_t* out_rows,
                      int32_t* out_parents, int64_t* nout, const BlockWs& W) {
-    hipLaunchKernelGGL(k_blk_find, dim3(grid_for(nf, 256, L.grid_cap)), dim3(256), 0, L.stream, B.jc, B.nzc, F, nf,
-                       W.q, W.qlen);
+    const double lg = B.nzc > 1 ? std::log2((double)B.nzc) : 1.0;
+    if (B.nzc > 0 && (double)nf * lg > (double)B.nzc) {
+        const int gm = grid_for(nf, 256, L.grid_cap);
+        hipLaunchKernelGGL(k_blk_mark, dim3(gm), dim3(256), 0, L.stream, F, nf, W.fmark, 0);
+        launch_scan(L.stream, JcInFrontier{B.jc, W.fmark}, (const uint64_t*)nullptr, B.nzc, W.partial,
+                    JcIndexSink{W.q, W.qlen});
+        hipLaunchKernelGGL(k_blk_mark, dim3(gm), dim3(256), 0, L.stream, F, nf, W.fmark, 1);
+    } else {
+        hipLaunchKernelGGL(k_blk_find, dim3(grid_for(nf, 256, L.grid_cap)), dim3(256), 0, L.stream, B.jc, B.nzc, F,
+                           nf, W.q, W.qlen);
+    }
     const int64_t qmax = nf < B.nzc ? nf : B.nzc;
     launch_scan(L.stream, QueueDegree<int64_t>{B.cp, W.q}, W.qlen, qmax, W.partial,
                 TileSink{W.scan, W.tiles, W.total});

@@ -11,6 +11,8 @@ namespace bfsk {
 
 // number of vertices of a CSR graph handle (0 for other handles)
 int64_t graph_vertices(const bfs_graph* g);
+// sets the calling thread's bfs_last_error() message
+void set_last_error(const char* msg);
 
 constexpr int WAVE = 64;
 constexpr int TD_BLOCK = 256;                 // threads per top-down expand workgroup
@@ -139,7 +141,7 @@ template <typename OffT>
 void launch_ms_td(const Launch& L, const OffT* off, const int32_t* cols, int64_t nnz, const int32_t* q, int64_t qlen,
                   int64_t total, int64_t* scan, int32_t* tiles, int64_t* partial, const uint64_t* F, uint64_t* N,
                   uint64_t* visited, uint64_t full, int32_t* qnext, int32_t* par_vm, uint16_t* lvl_vm,
-                  uint16_t level, int serial, uint64_t* slot, uint64_t* zslot);
+                  uint16_t level, int serial, uint64_t* hubmark, uint64_t* slot, uint64_t* zslot);
 template <typename OffT>
 void launch_ms_bu(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, const uint64_t* F, uint64_t* N,
                   uint64_t* visited, uint64_t full, const uint64_t* active_dev, int32_t* par_vm, uint16_t* lvl_vm,
@@ -168,6 +170,7 @@ struct BlockWs {
     int64_t* partial;
     uint32_t* spa;      // nrows complemented minimum parents, 0 = empty (kept zero between calls)
     uint64_t* occ;      // occupied rows (kept zero between calls)
+    uint64_t* fmark;    // frontier columns of a dense frontier (kept zero between calls)
     int32_t* bpar;
     uint64_t* bmask;
 };

@@ -23,7 +23,11 @@
 namespace bfsk {
 
 // counter slot words of a multi-source level
-enum { M_QLEN = 0, M_NNEXT = 1, M_MNEXT = 2, M_OR = 3, M_MFULL = 4, M_EXAM = 5 };
+enum { M_QLEN = 0, M_NNEXT = 1, M_MNEXT = 2, M_OR = 3, M_MFULL = 4, M_EXAM = 5, M_HUBS = 7 };
+
+// rows longer than this are not scanned by the resolve pass: their parents
+// come from the frontier side instead (k_ms_hub_resolve)
+constexpr int64_t MS_HUB_ROW = 512;
 
 __device__ __forceinline__ void or_reduce_add(uint64_t n, uint64_t m, uint64_t orv, uint64_t mfull, uint64_t exam,
                                               uint64_t* slot) {
@@ -274,7 +278,8 @@ __global__ __launch_bounds__(256) void k_ms_resolve(const OffT* __restrict__ off
                                                     const uint64_t* __restrict__ F, uint64_t* __restrict__ N,
                                                     uint64_t* __restrict__ visited, uint64_t full,
                                                     int32_t* __restrict__ par_vm, uint16_t* __restrict__ lvl_vm,
-                                                    uint16_t level, int serial, uint64_t* __restrict__ slot) {
+                                                    uint16_t level, int serial, uint64_t* __restrict__ hubmark,
+                                                    uint64_t* __restrict__ slot) {
     const int64_t qlen = (int64_t)*qlen_dev;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     uint64_t cn = 0, cm = 0, cor = 0, cfull = 0, cx = 0;
@@ -288,8 +293,24 @@ __global__ __launch_bounds__(256) void k_ms_resolve(const OffT* __restrict__ off
             beg = (int64_t)off[v];
             end = (int64_t)off[v + 1];
         }
+        // a long row would be scanned by one wave up to its first suppliers,
+        // which can lie anywhere in it: such vertices get their parents from
+        // the frontier's edges instead (an atomic minimum per new bit)
+        uint64_t scan_need = need;
+        if (i < qlen && need && end - beg > MS_HUB_ROW) {
+            atomicOr((unsigned long long*)&hubmark[v >> 6], 1ull << (v & 63));
+            uint64_t b = need;
+            while (b) {
+                const int j = __ffsll((unsigned long long)b) - 1;
+                b &= b - 1;
+                par_vm[v * 64 + j] = 0x7fffffff;
+                lvl_vm[v * 64 + j] = level;
+            }
+            atomicAdd((unsigned long long*)&slot[M_HUBS], 1ull);
+            scan_need = 0;
+        }
         int64_t ex = 0;
-        first_suppliers(cols, F, v, beg, end, need, serial, par_vm, lvl_vm, level, &ex);
+        first_suppliers(cols, F, v, beg, end, scan_need, serial, par_vm, lvl_vm, level, &ex);
         if (i < qlen) {
             const uint64_t vis = visited[v] | need;
             visited[v] = vis;
@@ -443,19 +464,90 @@ void launch_ms_init(const Launch& L, const OffT* off, int64_t n, int k, const in
                        q, slot0);
 }
 
+// parents of the marked long-row vertices, from the frontier side: every
+// frontier edge (u, v) into a marked v offers u to each bit of F[u] that is
+// new at v this level; the minimum stays.  Same edge tiles as the expansion.
+template <typename OffT>
+__global__ __launch_bounds__(TD_BLOCK) void k_ms_hub_resolve(
+    const OffT* __restrict__ off, const int32_t* __restrict__ cols, const int32_t* __restrict__ q, int64_t qlen,
+    const int64_t* __restrict__ scan, const int32_t* __restrict__ tile_start, int64_t total, int64_t nnz,
+    const uint64_t* __restrict__ F, const uint64_t* __restrict__ N, const uint64_t* __restrict__ hubmark,
+    int32_t* __restrict__ par_vm, const uint64_t* __restrict__ hubs) {
+    if (*hubs == 0) return;
+    __shared__ int32_t s_start[TD_TILE + 1];
+    __shared__ int64_t s_base[TD_TILE + 1];
+    __shared__ int32_t s_u[TD_TILE + 1];
+    const int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t e0 = t * TD_TILE;
+        const int64_t e1 = (e0 + TD_TILE < total) ? e0 + TD_TILE : total;
+        const int i0 = tile_start[t];
+        int nv = tile_start[t + 1] - i0 + 1;
+        if (nv > TD_TILE + 1) nv = TD_TILE + 1;
+        if (i0 < 0 || i0 >= qlen) nv = 0;
+        else if (nv > qlen - i0) nv = (int)(qlen - i0);
+        __syncthreads();
+        for (int j = threadIdx.x; j < nv; j += TD_BLOCK) {
+            const int32_t u = q[i0 + j];
+            const int64_t sc = scan[i0 + j];
+            const int64_t rel = sc - e0;
+            s_start[j] = rel < 0 ? 0 : (int32_t)rel;
+            s_base[j] = (int64_t)off[u] - sc;
+            s_u[j] = u;
+        }
+        __syncthreads();
+        for (int k = 0; k < TD_EPT; ++k) {
+            const int p = k * TD_BLOCK + threadIdx.x;
+            const int64_t e = e0 + p;
+            if (e >= e1 || nv == 0) continue;
+            int lo = 0, hi = nv - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_start[mid] <= p) lo = mid; else hi = mid - 1;
+            }
+            int64_t pos = s_base[lo] + e;
+            if (pos < 0 || pos >= nnz) continue;
+            const int32_t v = cols[pos];
+            if (!((hubmark[v >> 6] >> (v & 63)) & 1ull)) continue;
+            const int32_t u = s_u[lo];
+            uint64_t b = F[u] & N[v];
+            while (b) {
+                const int j = __ffsll((unsigned long long)b) - 1;
+                b &= b - 1;
+                atomicMin(&par_vm[(int64_t)v * 64 + j], u);
+            }
+        }
+    }
+}
+
+// clear the marks of the queued vertices (every marked vertex is queued)
+__global__ void k_ms_hub_clear(const int32_t* __restrict__ q, const uint64_t* __restrict__ qlen_dev,
+                               uint64_t* __restrict__ hubmark, const uint64_t* __restrict__ hubs) {
+    if (*hubs == 0) return;
+    const int64_t qlen = (int64_t)*qlen_dev;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < qlen; i += stride) hubmark[q[i] >> 6] = 0;
+}
+
 template <typename OffT>
 void launch_ms_td(const Launch& L, const OffT* off, const int32_t* cols, int64_t nnz, const int32_t* q, int64_t qlen,
                   int64_t total, int64_t* scan, int32_t* tiles, int64_t* partial, const uint64_t* F, uint64_t* N,
                   uint64_t* visited, uint64_t full, int32_t* qnext, int32_t* par_vm, uint16_t* lvl_vm,
-                  uint16_t level, int serial, uint64_t* slot, uint64_t* zslot) {
+                  uint16_t level, int serial, uint64_t* hubmark, uint64_t* slot, uint64_t* zslot) {
     launch_scan(L.stream, QueueDegree<OffT>{off, q}, (const uint64_t*)nullptr, qlen, partial,
                 TileSink{scan, tiles, nullptr});
     const int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
-    hipLaunchKernelGGL(k_ms_td_expand<OffT>, dim3(grid_for(ntiles, 1, L.grid_cap)), dim3(TD_BLOCK), 0, L.stream,
+    const int g = grid_for(ntiles, 1, L.grid_cap);
+    hipLaunchKernelGGL(k_ms_td_expand<OffT>, dim3(g), dim3(TD_BLOCK), 0, L.stream,
                        off, cols, q, qlen, scan, tiles, total, nnz, F, visited, N, qnext, slot, zslot);
     // the next queue's length is in slot[M_QLEN], written by the expand
     hipLaunchKernelGGL(k_ms_resolve<OffT>, dim3(L.grid_cap), dim3(256), 0, L.stream, off, cols, qnext,
-                       (const uint64_t*)&slot[M_QLEN], F, N, visited, full, par_vm, lvl_vm, level, serial, slot);
+                       (const uint64_t*)&slot[M_QLEN], F, N, visited, full, par_vm, lvl_vm, level, serial, hubmark,
+                       slot);
+    hipLaunchKernelGGL(k_ms_hub_resolve<OffT>, dim3(g), dim3(TD_BLOCK), 0, L.stream, off, cols, q, qlen, scan, tiles,
+                       total, nnz, F, N, hubmark, par_vm, (const uint64_t*)&slot[M_HUBS]);
+    hipLaunchKernelGGL(k_ms_hub_clear, dim3(L.grid_cap), dim3(256), 0, L.stream, qnext, (const uint64_t*)&slot[M_QLEN],
+                       hubmark, (const uint64_t*)&slot[M_HUBS]);
 }
 
 template <typename OffT>
@@ -489,7 +581,8 @@ void launch_ms_output(const Launch& L, int64_t n, int k, const int64_t* src, con
                                     uint64_t*);                                                                    \
     template void launch_ms_td<T>(const Launch&, const T*, const int32_t*, int64_t, const int32_t*, int64_t,       \
                                   int64_t, int64_t*, int32_t*, int64_t*, const uint64_t*, uint64_t*, uint64_t*,    \
-                                  uint64_t, int32_t*, int32_t*, uint16_t*, uint16_t, int, uint64_t*, uint64_t*);   \
+                                  uint64_t, int32_t*, int32_t*, uint16_t*, uint16_t, int, uint64_t*, uint64_t*,    \
+                                  uint64_t*);                                                                      \
     template void launch_ms_bu<T>(const Launch&, const T*, const int32_t*, int64_t, const uint64_t*, uint64_t*,    \
                                   uint64_t*, uint64_t, const uint64_t*, int32_t*, uint16_t*, uint16_t, int,        \
                                   uint64_t*, uint64_t*);

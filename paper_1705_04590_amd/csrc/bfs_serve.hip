@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -15,6 +16,7 @@
 #include <vector>
 
 #include "../../include/bfs_serve.h"
+
 #include "bfs_internal.h"
 
 namespace {
@@ -197,6 +199,9 @@ struct bfs_server {
                 st = bfs_run_multi(graphs[gid], srcs.data(), k, &o.opts, parent, depth, chunk, ws_bytes, stream,
                                    nullptr);
             }
+            // the batch's memory goes back to the pool only once every kernel
+            // that touches it has finished
+            if (hipStreamSynchronize(stream) != hipSuccess && st == BFS_OK) st = BFS_E_HIP;
             if (st == BFS_OK) {
                 bool copied = false;
                 for (int j = 0; j < k; ++j) {
@@ -270,7 +275,14 @@ bfs_status bfs_server_create(const bfs_server_opts* o, bfs_server** out) {
         return BFS_E_HIP;
     }
     void* base = nullptr;
-    if (hipMalloc(&base, o->hbm_budget) != hipSuccess) {
+    const hipError_t e = hipMalloc(&base, o->hbm_budget);
+    if (e != hipSuccess) {
+        char msg[160];
+        size_t fr = 0, tot = 0;
+        (void)hipMemGetInfo(&fr, &tot);
+        snprintf(msg, sizeof(msg), "server pool of %zu bytes: %s (%zu of %zu bytes free)", (size_t)o->hbm_budget,
+                 hipGetErrorString(e), fr, tot);
+        bfsk::set_last_error(msg);
         delete s;
         return BFS_E_HIP;
     }
@@ -411,7 +423,14 @@ void bfs_server_destroy(bfs_server* s) {
     s->cv_work.notify_all();
     for (auto& t : s->workers) t.join();
     for (auto& t : s->replayers) t.join();
-    if (s->pool.base) (void)hipFree(s->pool.base);
+    if (s->pool.base) {
+        const hipError_t e = hipFree(s->pool.base);
+        if (e != hipSuccess) {
+            char msg[128];
+            snprintf(msg, sizeof(msg), "server pool release: %s", hipGetErrorString(e));
+            bfsk::set_last_error(msg);
+        }
+    }
     delete s;
 }
 

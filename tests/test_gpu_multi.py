@@ -131,3 +131,32 @@ def test_multi_errors():
     with pytest.raises(bfs.BfsError) as e:
         bfs.bfs_run_multi(mg.g, [0], None, dep, ws[:1000])
     assert e.value.status == 7
+
+
+def test_multi_long_rows_get_minimum_parents(orc):
+    """Vertices whose rows exceed the resolve pass's scan limit take their
+    parents from the frontier side: hubs of several stars joined in a ring,
+    sources on leaves and on hubs, top-down only and direction-optimizing."""
+    hubs, leaves = 6, 900
+    n = hubs * (leaves + 1)
+    a, b = [], []
+    for h in range(hubs):
+        c = h * (leaves + 1)
+        a += [c] * leaves
+        b += list(range(c + 1, c + 1 + leaves))
+        a.append(c)
+        b.append(((h + 1) % hubs) * (leaves + 1))
+    # leaves of neighbouring stars share some extra edges, so a hub has
+    # several frontier neighbours and the minimum matters
+    rng = np.random.default_rng(3)
+    for _ in range(2000):
+        h = int(rng.integers(0, hubs))
+        a.append(h * (leaves + 1) + 1 + int(rng.integers(0, leaves)))
+        b.append(((h + 1) % hubs) * (leaves + 1) + 1 + int(rng.integers(0, leaves)))
+    off, cols = graphgen.csr_from_edges(n, np.array(a), np.array(b))
+    assert np.diff(off).max() > 512
+    mg = MG(off, cols)
+    srcs = [int(x) for x in rng.choice(np.flatnonzero(np.diff(off) > 0), 60, replace=False)] + [0, leaves + 1]
+    for direction in (0, 1):
+        p, d, _ = mg.multi(srcs, dir=direction)
+        check_all(orc, mg, srcs, p, d)
