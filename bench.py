@@ -400,7 +400,7 @@ def main():
     ap.add_argument("--beta", type=float, default=18.0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="time only the given alpha/beta and default knobs (no autotuner pass)")
-    ap.add_argument("--tune-sources", type=int, default=8, help="tuning sources (seed 99, distinct from evaluation)")
+    ap.add_argument("--tune-sources", type=int, default=16, help="tuning sources (seed 99, distinct from evaluation)")
     ap.add_argument("--retune", action="store_true", help="search again and overwrite the cached entry")
     ap.add_argument("--tune-cache", default=TUNE_CACHE, help="autotune cache file")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="budget of the oracle CPU baseline")
