@@ -69,6 +69,7 @@ struct bfs_graph {
     // vertex, and for any-parent searches {degree, three highest-degree neighbours}
     int4* d_head = nullptr;
     int4* d_hub = nullptr;
+    uint32_t* d_nbase = nullptr;   // per word: vertices with edges before it (head record index base)
     // workgroups of the persistent top-down engine that fit on the device
     int persist_groups_max = 1;
     // host metadata
@@ -511,8 +512,8 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             HIP_TRY(T.begin(BFS_K_BU_SWEEP));
             // any-parent searches probe the highest-degree neighbours first
             const bool hub = claim_mode != CLAIM_MIN && o.bu_head == 0;
-            launch_bu_sweep<OffT>(L, hub ? g->d_hub : g->d_head, hub, off, g->cols, fbits, nbits, visited, vprev,
-                                  parent, depth, W, next_depth, serial, slot, zslot);
+            launch_bu_sweep<OffT>(L, hub ? g->d_hub : g->d_head, hub, g->d_iso, g->d_nbase, off, g->cols, fbits,
+                                  nbits, visited, vprev, parent, depth, W, next_depth, serial, slot, zslot);
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_BU_SWEEP, level));
             if (st) st->launches[BFS_K_BU_SWEEP] += 1;
@@ -727,11 +728,20 @@ bfs_status build_derived(bfs_graph* g, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(g->h_buf, d_count, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     g->isolated = (int64_t)g->h_buf[0];
-    HIP_TRY(hipMalloc((void**)&g->d_head, sizeof(int4) * (size_t)g->n));
-    launch_row_heads<OffT>(L, (const OffT*)g->off, g->cols, g->n, g->d_head);
+    const int64_t nrec = g->n - g->isolated;
+    HIP_TRY(hipMalloc((void**)&g->d_nbase, sizeof(uint32_t) * (size_t)W));
+    struct Scratch {   // scan partials, released on every return
+        int64_t* p = nullptr;
+        ~Scratch() { if (p) (void)hipFree(p); }
+    } partial;
+    HIP_TRY(hipMalloc((void**)&partial.p, sizeof(int64_t) * (size_t)((W + SCAN_TILE - 1) / SCAN_TILE + 2)));
+    launch_head_index(L, g->d_iso, W, g->d_nbase, partial.p);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMalloc((void**)&g->d_hub, sizeof(int4) * (size_t)g->n));
-    launch_hub_heads<OffT>(L, (const OffT*)g->off, g->cols, g->d_head, g->n, g->d_hub);
+    HIP_TRY(hipMalloc((void**)&g->d_head, sizeof(int4) * (size_t)(nrec > 0 ? nrec : 1)));
+    launch_row_heads<OffT>(L, (const OffT*)g->off, g->cols, g->n, g->d_iso, g->d_nbase, g->d_head);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMalloc((void**)&g->d_hub, sizeof(int4) * (size_t)(nrec > 0 ? nrec : 1)));
+    launch_hub_heads<OffT>(L, (const OffT*)g->off, g->cols, g->n, g->d_iso, g->d_nbase, g->d_hub);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     return BFS_OK;
@@ -914,6 +924,7 @@ void bfs_destroy_graph(bfs_graph* g) {
     if (g->d_iso) (void)hipFree(g->d_iso);
     if (g->d_head) (void)hipFree(g->d_head);
     if (g->d_hub) (void)hipFree(g->d_hub);
+    if (g->d_nbase) (void)hipFree(g->d_nbase);
     if (g->h_buf) (void)hipHostFree(g->h_buf);
     delete g;
 }

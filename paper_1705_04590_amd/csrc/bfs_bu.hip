@@ -50,16 +50,19 @@ __device__ __forceinline__ uint64_t stream_load(const uint64_t* p) { return __bu
 // row from its start.
 template <typename OffT, int HUB>
 __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
-    const int4* __restrict__ head, const OffT* __restrict__ off, const int32_t* __restrict__ cols,
+    const int4* __restrict__ head, const uint64_t* __restrict__ iso, const uint32_t* __restrict__ nbase,
+    const OffT* __restrict__ off, const int32_t* __restrict__ cols,
     const uint64_t* __restrict__ fbits, uint64_t* __restrict__ nbits, uint64_t* __restrict__ visited,
     uint64_t* __restrict__ vprev, int32_t* __restrict__ parent, int32_t* __restrict__ depth, int64_t W, int GW,
     int32_t next_depth, int serial_len, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot) {
     __shared__ int32_t s_list[BU_BLOCK / WAVE][BU_WIN];
+    __shared__ int32_t s_hidx[BU_BLOCK / WAVE][BU_WIN];
     __shared__ unsigned long long s_nb[BU_BLOCK / WAVE][WAVE];
     zero_slot(zslot);
     const int lane = lane_id();
     const int wid = threadIdx.x / WAVE;
     int32_t* list = s_list[wid];
+    int32_t* hlist = s_hidx[wid];
     unsigned long long* nbw = s_nb[wid];
     const int64_t G = (W + GW - 1) / GW;
     const int64_t nwaves = (int64_t)gridDim.x * (BU_BLOCK / WAVE);
@@ -79,6 +82,9 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
         const int64_t w = w0 + lane;
         const bool mine = lane < GW && w < W;
         const uint64_t wv = mine ? stream_load(&visited[w]) : ~0ull;
+        // head records exist for vertices with edges only: index = rank among them
+        const uint64_t hasrow = mine ? ~stream_load(&iso[w]) : 0ull;
+        const uint32_t hbase = mine ? nbase[w] : 0u;
         const int cnt = __popcll(~wv);
         const int incl = wave_incl_scan(cnt);
         const int tot = __shfl(incl, WAVE - 1, WAVE);
@@ -95,20 +101,21 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
                     const int b = __ffsll((unsigned long long)x) - 1;
                     x &= x - 1;
                     list[idx - lo] = (int32_t)(w * WAVE + b);
+                    hlist[idx - lo] = (int32_t)(hbase + (uint32_t)__popcll(hasrow & ((1ull << b) - 1ull)));
                 }
             }
             wave_lds_sync();
             // heads of the first round; later rounds are prefetched one ahead
             int32_t v_next = lane < nw ? list[lane] : 0;
             int4 h_next = make_int4(0, -1, -1, -1);
-            if (lane < nw) h_next = head[v_next];
+            if (lane < nw) h_next = head[hlist[lane]];
             for (int r = 0; r < nw; r += WAVE) {
                 const bool act = r + lane < nw;
                 const int32_t v = v_next;
                 const int4 h = h_next;
                 if (r + WAVE + lane < nw) {
                     v_next = list[r + WAVE + lane];
-                    h_next = head[v_next];
+                    h_next = head[hlist[r + WAVE + lane]];
                 }
                 const int deg = act ? h.x : 0;
                 int32_t par = -1;
@@ -200,41 +207,67 @@ static int group_words(int64_t W, int waves) {
 }
 
 template <typename OffT>
-void launch_bu_sweep(const Launch& L, const int4* head, bool hub, const OffT* off, const int32_t* cols,
-                     const uint64_t* fbits, uint64_t* nbits, uint64_t* visited, uint64_t* vprev, int32_t* parent,
-                     int32_t* depth, int64_t W, int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot) {
+void launch_bu_sweep(const Launch& L, const int4* head, bool hub, const uint64_t* iso, const uint32_t* nbase,
+                     const OffT* off, const int32_t* cols, const uint64_t* fbits, uint64_t* nbits, uint64_t* visited,
+                     uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W, int32_t next_depth, int serial_len,
+                     uint64_t* slot, uint64_t* zslot) {
     const int gw = group_words(W, L.grid_cap * (BU_BLOCK / WAVE));
     const int64_t G = (W + gw - 1) / gw;
     const int g = grid_for(G, BU_BLOCK / WAVE, L.grid_cap);
     if (hub)
-        hipLaunchKernelGGL((k_bu_sweep<OffT, 1>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, off, cols, fbits, nbits,
+        hipLaunchKernelGGL((k_bu_sweep<OffT, 1>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off, cols,
+                           fbits, nbits,
                            visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot, zslot);
     else
-        hipLaunchKernelGGL((k_bu_sweep<OffT, 0>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, off, cols, fbits, nbits,
+        hipLaunchKernelGGL((k_bu_sweep<OffT, 0>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off, cols,
+                           fbits, nbits,
                            visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot, zslot);
 }
 
 // ------------------------------------------------------------------ row heads
+// index of vertex v's head record: its rank among the vertices with edges
+__device__ __forceinline__ int64_t head_index(const uint64_t* iso, const uint32_t* nbase, int64_t v) {
+    return (int64_t)nbase[v >> 6] + __popcll(~iso[v >> 6] & ((1ull << (v & 63)) - 1ull));
+}
+
 template <typename OffT>
 __global__ void k_row_heads(const OffT* __restrict__ off, const int32_t* __restrict__ cols, int64_t n,
+                            const uint64_t* __restrict__ iso, const uint32_t* __restrict__ nbase,
                             int4* __restrict__ head) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
         const int64_t b = (int64_t)off[v];
         const int64_t d = (int64_t)off[v + 1] - b;
+        if (d == 0) continue;
         int4 h;
         h.x = (int32_t)d;
         h.y = d > 0 ? cols[b] : -1;
         h.z = d > 1 ? cols[b + 1] : -1;
         h.w = d > 2 ? cols[b + 2] : -1;
-        head[v] = h;
+        head[head_index(iso, nbase, v)] = h;
     }
 }
 
 template <typename OffT>
-void launch_row_heads(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, int4* head) {
+void launch_row_heads(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, const uint64_t* iso,
+                      const uint32_t* nbase, int4* head) {
     hipLaunchKernelGGL(k_row_heads<OffT>, dim3(grid_for(n, 256, L.grid_cap)), dim3(256), 0, L.stream, off, cols, n,
-                       head);
+                       iso, nbase, head);
+}
+
+// nbase[w] = vertices with edges in words [0, w)
+struct RowsInWord {
+    const uint64_t* iso;
+    __device__ int64_t operator()(int64_t w) const { return __popcll(~iso[w]); }
+};
+struct BaseSink {
+    uint32_t* nbase;
+    __device__ void item(int64_t w, int64_t before, int64_t) const { nbase[w] = (uint32_t)before; }
+    __device__ void last(int64_t, int64_t) const {}
+};
+
+void launch_head_index(const Launch& L, const uint64_t* iso, int64_t W, uint32_t* nbase, int64_t* partial) {
+    launch_scan(L.stream, RowsInWord{iso}, (const uint64_t*)nullptr, W, partial, BaseSink{nbase});
 }
 
 // hub heads: {deg, the three neighbours of highest degree (ties: smaller id)}
@@ -247,17 +280,19 @@ __device__ __forceinline__ bool hub_before(int32_t da, int32_t a, int32_t db, in
 }
 
 template <typename OffT>
-__global__ void k_hub_heads(const OffT* __restrict__ off, const int32_t* __restrict__ cols,
-                            const int4* __restrict__ head, int64_t n, int4* __restrict__ hub) {
+__global__ void k_hub_heads(const OffT* __restrict__ off, const int32_t* __restrict__ cols, int64_t n,
+                            const uint64_t* __restrict__ iso, const uint32_t* __restrict__ nbase,
+                            int4* __restrict__ hub) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
         const int64_t b = (int64_t)off[v];
         const int64_t d = (int64_t)off[v + 1] - b;
+        if (d == 0) continue;
         const int64_t m = d < HUB_SCAN ? d : HUB_SCAN;
         int32_t c0 = -1, c1 = -1, c2 = -1, d0 = -1, d1 = -1, d2 = -1;
         for (int64_t i = 0; i < m; ++i) {
             const int32_t c = cols[b + i];
-            const int32_t dc = head[c].x;
+            const int32_t dc = (int32_t)((int64_t)off[c + 1] - (int64_t)off[c]);
             if (hub_before(dc, c, d0, c0) || c0 < 0) {
                 c2 = c1; d2 = d1; c1 = c0; d1 = d0; c0 = c; d0 = dc;
             } else if (hub_before(dc, c, d1, c1) || c1 < 0) {
@@ -266,22 +301,25 @@ __global__ void k_hub_heads(const OffT* __restrict__ off, const int32_t* __restr
                 c2 = c; d2 = dc;
             }
         }
-        hub[v] = make_int4((int32_t)d, c0, c1, c2);
+        hub[head_index(iso, nbase, v)] = make_int4((int32_t)d, c0, c1, c2);
     }
 }
 
 template <typename OffT>
-void launch_hub_heads(const Launch& L, const OffT* off, const int32_t* cols, const int4* head, int64_t n, int4* hub) {
-    hipLaunchKernelGGL(k_hub_heads<OffT>, dim3(grid_for(n, 256, L.grid_cap)), dim3(256), 0, L.stream, off, cols, head,
-                       n, hub);
+void launch_hub_heads(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, const uint64_t* iso,
+                      const uint32_t* nbase, int4* hub) {
+    hipLaunchKernelGGL(k_hub_heads<OffT>, dim3(grid_for(n, 256, L.grid_cap)), dim3(256), 0, L.stream, off, cols, n,
+                       iso, nbase, hub);
 }
 
 #define BFS_BU_INST(T)                                                                                           \
-    template void launch_bu_sweep<T>(const Launch&, const int4*, bool, const T*, const int32_t*,               \
-                                     const uint64_t*, uint64_t*, uint64_t*, uint64_t*, int32_t*, int32_t*,      \
-                                     int64_t, int32_t, int, uint64_t*, uint64_t*);                               \
-    template void launch_row_heads<T>(const Launch&, const T*, const int32_t*, int64_t, int4*);                 \
-    template void launch_hub_heads<T>(const Launch&, const T*, const int32_t*, const int4*, int64_t, int4*);
+    template void launch_bu_sweep<T>(const Launch&, const int4*, bool, const uint64_t*, const uint32_t*,         \
+                                     const T*, const int32_t*, const uint64_t*, uint64_t*, uint64_t*, uint64_t*, \
+                                     int32_t*, int32_t*, int64_t, int32_t, int, uint64_t*, uint64_t*);           \
+    template void launch_row_heads<T>(const Launch&, const T*, const int32_t*, int64_t, const uint64_t*,        \
+                                      const uint32_t*, int4*);                                                   \
+    template void launch_hub_heads<T>(const Launch&, const T*, const int32_t*, int64_t, const uint64_t*,        \
+                                      const uint32_t*, int4*);
 BFS_BU_INST(int32_t)
 BFS_BU_INST(int64_t)
 

@@ -78,15 +78,22 @@ void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t*
                       int32_t next_depth);
 
 template <typename OffT>
-void launch_bu_sweep(const Launch& L, const int4* head, bool hub, const OffT* off, const int32_t* cols,
-                     const uint64_t* fbits, uint64_t* nbits, uint64_t* visited, uint64_t* vprev, int32_t* parent,
-                     int32_t* depth, int64_t W, int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot);
-// per-vertex row heads {degree, first three entries (-1 when absent)}
+void launch_bu_sweep(const Launch& L, const int4* head, bool hub, const uint64_t* iso, const uint32_t* nbase,
+                     const OffT* off, const int32_t* cols, const uint64_t* fbits, uint64_t* nbits, uint64_t* visited,
+                     uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W, int32_t next_depth, int serial_len,
+                     uint64_t* slot, uint64_t* zslot);
+// Head records exist for the vertices with edges only, stored by rank among
+// them: record of v = nbase[v/64] + (vertices with edges before v in its word).
+// nbase (W entries) from the isolated-vertex bitmap; partial: scan scratch
+void launch_head_index(const Launch& L, const uint64_t* iso, int64_t W, uint32_t* nbase, int64_t* partial);
+// row heads {degree, first three entries (-1 when absent)}
 template <typename OffT>
-void launch_row_heads(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, int4* head);
-// per-vertex hub heads {degree, three highest-degree neighbours (-1 when absent)}
+void launch_row_heads(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, const uint64_t* iso,
+                      const uint32_t* nbase, int4* head);
+// hub heads {degree, three highest-degree neighbours (-1 when absent)}
 template <typename OffT>
-void launch_hub_heads(const Launch& L, const OffT* off, const int32_t* cols, const int4* head, int64_t n, int4* hub);
+void launch_hub_heads(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, const uint64_t* iso,
+                      const uint32_t* nbase, int4* hub);
 
 void launch_clear_words(const Launch& L, uint64_t* w, int64_t nw);
 // host mailbox: dst[1..nw] = src[0..nw), then dst[0] = seq (dst: coherent pinned host memory)
