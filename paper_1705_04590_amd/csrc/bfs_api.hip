@@ -234,6 +234,7 @@ BlockArgs block_args(const bfs_graph* g) {
     B.nrows = g->nrows; B.ncols = g->ncols; B.col_base = g->col_base;
     B.nzc = g->nzc; B.nzr = g->nzr; B.nnz = g->nnz;
     B.jc = g->jc; B.ir = g->ir; B.jr = g->jr; B.ic = g->ic; B.cp = g->cp; B.rp = g->rp;
+    B.sorted = (g->flags & BFS_GRAPH_SORTED) != 0;
     return B;
 }
 

@@ -4,9 +4,13 @@
 // Top-down (Alg. 3, the sparse-matrix sparse-vector product on the
 // (select2nd, min) semiring of Section 4.2, with a sparse accumulator as in
 // Section 5.2):
-//   1. every frontier column is looked up in JC (binary search; for dense
-//      frontiers one pass over JC against a column bitmap of F instead); the
-//      JC indices found are compacted into a queue
+//   0. (dense frontiers, more than 1/32 of the columns, sorted block with its
+//      row-compressed copy) the result is computed from the row side instead:
+//      a first-hit sweep of every row against a bitmap of F, the pull form of
+//      the same product, with no accumulator and no atomics
+//   1. every frontier column is looked up in JC (binary search; for frontiers
+//      where |F| log2 nzc > nzc one pass over JC against a column bitmap of F
+//      instead); the JC indices found are compacted into a queue
 //   2. a prefix sum over their column lengths splits all their entries into
 //      fixed tiles (the same edge-balanced tiling as the whole-graph
 //      top-down step)
@@ -174,6 +178,10 @@ __global__ void k_blk_range(const int32_t* __restrict__ jr, int64_t nzr, int64_t
     range[2] = (uint64_t)((bound[1] - bound[0] + 63) / 64);
 }
 
+// COMP = 1: rows with their completed bit set are skipped and found rows set
+// it (Alg. 4).  COMP = 0: every row is scanned and `completed` is unused (the
+// pull form of the top-down step, see launch_block_td).
+template <int COMP>
 __global__ __launch_bounds__(BU_BLOCK) void k_blk_bu(
     const int32_t* __restrict__ jr, const int64_t* __restrict__ rp, const int32_t* __restrict__ ic,
     const uint64_t* __restrict__ range, const uint64_t* __restrict__ fbits, uint64_t* __restrict__ completed,
@@ -189,7 +197,7 @@ __global__ __launch_bounds__(BU_BLOCK) void k_blk_bu(
         int64_t beg = 0, end = 0;
         if (active) {
             r = jr[t];
-            active = !((completed[r >> 6] >> (r & 63)) & 1ull);
+            if (COMP) active = !((completed[r >> 6] >> (r & 63)) & 1ull);
         }
         if (active) {
             beg = rp[t];
@@ -231,7 +239,7 @@ __global__ __launch_bounds__(BU_BLOCK) void k_blk_bu(
         if (lane == 0) bmask[c] = fm;
         if (found) {
             bpar[c * WAVE + lane] = (int32_t)(col_base + par);
-            atomicOr((unsigned long long*)&completed[r >> 6], 1ull << (r & 63));
+            if (COMP) atomicOr((unsigned long long*)&completed[r >> 6], 1ull << (r & 63));
         }
     }
 }
@@ -293,6 +301,24 @@ struct JcIndexSink {
 // ---------------------------------------------------------------- launchers
 void launch_block_td(const Launch& L, const BlockArgs& B, const int32_t* F, int64_t nf, int32_t* out_rows,
                      int32_t* out_parents, int64_t* nout, const BlockWs& W) {
+    // A dense frontier (more than 1/32 of the columns): the same result from
+    // the row side.  Each row's minimum frontier column is the first frontier
+    // column of its ascending row, so a first-hit sweep of the row-compressed
+    // copy against a bitmap of F gives the (row, parent) pairs in row order
+    // with no accumulator and no atomics.
+    if (B.jr && B.sorted && B.nzr > 0 && nf * 32 > B.ncols) {
+        const int gm = grid_for(nf, 256, L.grid_cap);
+        hipLaunchKernelGGL(k_blk_mark, dim3(gm), dim3(256), 0, L.stream, F, nf, W.fmark, 0);
+        hipLaunchKernelGGL(k_blk_range, dim3(1), dim3(1), 0, L.stream, B.jr, B.nzr, (int64_t)0, B.nrows, W.range);
+        const int64_t chunks_max = (B.nzr + WAVE - 1) / WAVE;
+        hipLaunchKernelGGL(k_blk_bu<0>, dim3(grid_for(chunks_max, BU_BLOCK / WAVE, L.grid_cap)), dim3(BU_BLOCK), 0,
+                           L.stream, B.jr, B.rp, B.ic, W.range, W.fmark, nullptr, B.col_base, B.ncols, 16, W.bpar,
+                           W.bmask);
+        launch_scan(L.stream, WordPopc{W.bmask}, W.range + 2, chunks_max, W.partial,
+                    ChunkEmit{W.bmask, W.bpar, B.jr, W.range, out_rows, out_parents, nout});
+        hipLaunchKernelGGL(k_blk_mark, dim3(gm), dim3(256), 0, L.stream, F, nf, W.fmark, 1);
+        return;
+    }
     const double lg = B.nzc > 1 ? std::log2((double)B.nzc) : 1.0;
     if (B.nzc > 0 && (double)nf * lg > (double)B.nzc) {
         const int gm = grid_for(nf, 256, L.grid_cap);
@@ -321,7 +347,7 @@ void launch_block_bu(const Launch& L, const BlockArgs& B, const uint64_t* fbits,
                      int64_t* nout, const BlockWs& W) {
     hipLaunchKernelGGL(k_blk_range, dim3(1), dim3(1), 0, L.stream, B.jr, B.nzr, row_lo, row_hi, W.range);
     const int64_t chunks_max = (B.nzr + WAVE - 1) / WAVE;
-    hipLaunchKernelGGL(k_blk_bu, dim3(grid_for(chunks_max, BU_BLOCK / WAVE, L.grid_cap)), dim3(BU_BLOCK), 0,
+    hipLaunchKernelGGL(k_blk_bu<1>, dim3(grid_for(chunks_max, BU_BLOCK / WAVE, L.grid_cap)), dim3(BU_BLOCK), 0,
                        L.stream, B.jr, B.rp, B.ic, W.range, fbits, completed, B.col_base, B.ncols, serial_len,
                        W.bpar, W.bmask);
     launch_scan(L.stream, WordPopc{W.bmask}, W.range + 2, chunks_max, W.partial,

@@ -163,6 +163,7 @@ void launch_ms_output(const Launch& L, int64_t n, int k, const int64_t* src, con
 // ---- DCSC block ----------------------------------------------------------
 struct BlockArgs {
     int64_t nrows, ncols, col_base, nzc, nzr, nnz;
+    bool sorted;   // entries ascending inside every column and row
     const int32_t *jc, *ir, *jr, *ic;
     const int64_t *cp, *rp;
 };

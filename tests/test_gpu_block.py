@@ -123,6 +123,31 @@ def test_block_sparse_frontiers(orc, density):
         assert np.array_equal(r, er) and np.array_equal(p, ep) and np.array_equal(c2, ec)
 
 
+@pytest.mark.parametrize("density", [0.04, 0.3, 1.0])
+def test_dense_block_frontier_all_layouts(orc, density):
+    """Dense frontiers take the row scan (row copy, sorted), the JC scan (no row copy) or
+    the JC scan over unsorted-flagged rows; all give the oracle's minimum parents."""
+    scale = 16
+    n = 1 << scale
+    R = C = n // 4
+    blk = graphgen.kronecker_block(scale, R, R, 2 * C, C, seed=7)
+    k = max(1, int(round(density * C)))
+    fr = graphgen.random_sorted_subset(C, k, seed=8)
+    layouts = [dict(row_major=True), dict(row_major=False),
+               dict(row_major=True, flags=bfs.BFS_GRAPH_VALIDATE)]
+    er = ep = None
+    for kw in layouts:
+        db = DevBlock(blk, R, C, R, 2 * C, **kw)
+        if er is None:
+            er, ep = orc.block_td(R, C, db.erow, db.ecol, 2 * C, fr)
+        r, p = db.td(fr)
+        assert np.array_equal(r, er) and np.array_equal(p, ep), kw
+        # the frontier marks are cleared: a sparse call afterwards is unaffected
+        r, p = db.td(fr[:3])
+        er3, ep3 = orc.block_td(R, C, db.erow, db.ecol, 2 * C, fr[:3])
+        assert np.array_equal(r, er3) and np.array_equal(p, ep3), kw
+
+
 def test_accumulator_is_reset_between_calls(orc):
     off, cols = graphgen.kronecker(13, seed=6)
     n = off.size - 1
