@@ -105,7 +105,7 @@ typedef struct {
     int32_t small_edges;   /* top-down levels with at most this many frontier
                               edges run back to back inside one persistent
                               workgroup with no host round trip (0 = default
-                              4096, negative = no persistent engine at all)      */
+                              1024, negative = no persistent engine at all)      */
     int32_t persist_edges; /* ... and up to this many inside persist_groups
                               workgroups separated by grid barriers (0 = default
                               65536)                                             */
