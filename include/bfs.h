@@ -111,9 +111,16 @@ typedef struct {
                               65536)                                             */
     int32_t persist_groups;/* workgroups of that engine (0 = default 64; capped
                               by what fits on the device at once)                */
-    int32_t bu_head;       /* bottom-up, ANY parents: 0 = probe each vertex's
-                              three highest-degree neighbours first, 1 = its
-                              first three row entries (MIN always uses these)    */
+    int32_t bu_head;       /* bottom-up, ANY parents, what each vertex probes
+                              before scanning its row: 2 = its three
+                              highest-degree neighbours; 3 = its two
+                              highest-degree neighbours, those among the graph's
+                              hubs (fewer than 65536 vertices of highest degree)
+                              in an on-chip copy of the hubs' frontier bits;
+                              0 (default) = 3 on a level entered from top-down
+                              when the frontier bitmap (n/8 bytes) is larger
+                              than the device's L2 cache, else 2; 1 = its first
+                              three row entries (MIN always uses these)        */
     int32_t reserved[4];
 } bfs_opts;
 

@@ -7,7 +7,8 @@ direction-invariant; the GPU tests check both):
   grid_blocks   workgroup cap of the grid-stride kernels
   td_claim      top-down claim: fetch-or on the visited bitmap or CAS on parent
   small_edges   persistent top-down engine on (0, default caps) or off (-1)
-  bu_head       bottom-up probe order for ANY parents: highest-degree neighbours (0) or row order (1)
+  bu_head       bottom-up probes for ANY parents: automatic (0), row order (1),
+                three highest-degree neighbours (2), two hub-ranked neighbours (3)
 
 The search is a coordinate descent: (alpha, beta) on a grid first, then each
 remaining knob in turn, every candidate timed as the mean wall time of the
@@ -31,7 +32,7 @@ SERIALS = (16, 4, 8, 32)
 GRIDS = (2048, 1024, 4096)
 CLAIMS = (0, 1)
 ENGINE = (0, -1)
-HEADS = (0, 1)
+HEADS = (0, 1, 2, 3)
 
 
 def _key(g, k: int) -> str:

@@ -69,6 +69,12 @@ struct bfs_graph {
     // vertex, and for any-parent searches {degree, three highest-degree neighbours}
     int4* d_head = nullptr;
     int4* d_hub = nullptr;
+    // hubs (the < HUB_BITS vertices of highest degree, by a degree threshold),
+    // in id order, and the hub heads with the ranks of their two hubs
+    int32_t* d_hubid = nullptr;
+    int4* d_hubr = nullptr;
+    int nhub = 0;
+    bool hub_auto = false;   // frontier bitmap larger than the L2: ranked probes by default
     uint32_t* d_nbase = nullptr;   // per word: vertices with edges before it (head record index base)
     // workgroups of the persistent top-down engine that fit on the device
     int persist_groups_max = 1;
@@ -151,7 +157,7 @@ bfs_status readback(HostCtx* c, hipStream_t s, const void* src, int nw, const ui
 // -------------------------------------------------------------- workspace layout
 struct SingleLayout {
     size_t counters, pctl, pctr, small, ctl_end, rec, visited, vprev, fbits, nbits, claim, q0, q1, scan, tiles, partial,
-        total;
+        hb, total;
 };
 
 SingleLayout single_layout(const bfs_graph* g) {
@@ -179,6 +185,7 @@ SingleLayout single_layout(const bfs_graph* g) {
     L.scan = o; o = align_up(o + sizeof(int64_t) * (size_t)(n + 2));
     L.tiles = o; o = align_up(o + sizeof(int32_t) * (size_t)(ntiles + 2));
     L.partial = o; o = align_up(o + sizeof(int64_t) * (size_t)((n + SCAN_TILE - 1) / SCAN_TILE + 2));
+    L.hb = o; o = align_up(o + sizeof(uint64_t) * (HUB_BITS / 64));
     L.total = o;
     return L;
 }
@@ -509,12 +516,22 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                 if (st) st->launches[BFS_K_CONVERT] += 2;
                 fbits_stale = false;
             }
+            const bool from_td = fmt_queue;   // the previous level ran top-down
             fmt_queue = false;
             HIP_TRY(T.begin(BFS_K_BU_SWEEP));
-            // any-parent searches probe the highest-degree neighbours first
-            const bool hub = claim_mode != CLAIM_MIN && o.bu_head == 0;
-            launch_bu_sweep<OffT>(L, hub ? g->d_hub : g->d_head, hub, g->d_iso, g->d_nbase, off, g->cols, fbits,
-                                  nbits, visited, vprev, parent, depth, W, next_depth, serial, slot, zslot);
+            // any-parent searches probe the highest-degree neighbours first.
+            // On a bottom-up level entered from top-down (small frontier, many
+            // misses) of a graph whose frontier bitmap exceeds the L2, the two
+            // hub neighbours are probed in an LDS copy of the hubs' frontier
+            // bits; later levels (large frontiers, nearly all hits on the first
+            // hub) keep three hubs and skip the per-level gather.
+            const bool ranked = g->nhub > 0 && (o.bu_head == 3 || (o.bu_head == 0 && from_td && g->hub_auto));
+            const int hk = claim_mode == CLAIM_MIN || o.bu_head == 1 ? 0 : ranked ? 2 : 1;
+            uint64_t* hb = (uint64_t*)(ws + Lo.hb);
+            if (hk == 2) launch_hub_gather(L, fbits, g->d_hubid, g->nhub, hb);
+            launch_bu_sweep<OffT>(L, hk == 2 ? g->d_hubr : hk == 1 ? g->d_hub : g->d_head, hk, g->d_iso, g->d_nbase,
+                                  off, g->cols, fbits, hb, nbits, visited, vprev, parent, depth, W, next_depth, serial,
+                                  slot, zslot);
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_BU_SWEEP, level));
             if (st) st->launches[BFS_K_BU_SWEEP] += 1;
@@ -744,6 +761,35 @@ bfs_status build_derived(bfs_graph* g, hipStream_t s) {
     HIP_TRY(hipMalloc((void**)&g->d_hub, sizeof(int4) * (size_t)(nrec > 0 ? nrec : 1)));
     launch_hub_heads<OffT>(L, (const OffT*)g->off, g->cols, g->n, g->d_iso, g->d_nbase, g->d_hub);
     HIP_TRY(hipGetLastError());
+    // hubs: the smallest degree threshold that leaves fewer than HUB_BITS
+    // vertices at or above it (none when even the top histogram bin is larger)
+    struct Tmp {
+        void* p = nullptr;
+        ~Tmp() { if (p) (void)hipFree(p); }
+    } hist, mask, hbase;
+    HIP_TRY(hipMalloc(&hist.p, sizeof(uint32_t) * HUB_HIST_BINS));
+    HIP_TRY(hipMemsetAsync(hist.p, 0, sizeof(uint32_t) * HUB_HIST_BINS, s));
+    launch_deg_hist<OffT>(L, (const OffT*)g->off, g->n, (uint32_t*)hist.p, HUB_HIST_BINS);
+    HIP_TRY(hipGetLastError());
+    std::vector<uint32_t> hh(HUB_HIST_BINS);
+    HIP_TRY(hipMemcpyAsync(hh.data(), hist.p, sizeof(uint32_t) * HUB_HIST_BINS, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int64_t nhub = 0, thr = 0;
+    for (int64_t d = HUB_HIST_BINS - 1; d >= 1; --d) {
+        if (nhub + hh[d] > HUB_BITS - 1) break;
+        nhub += hh[d];
+        thr = d;
+    }
+    if (nhub > 0) {
+        HIP_TRY(hipMalloc(&mask.p, sizeof(uint64_t) * (size_t)W));
+        HIP_TRY(hipMalloc(&hbase.p, sizeof(uint32_t) * (size_t)W));
+        HIP_TRY(hipMalloc((void**)&g->d_hubid, sizeof(int32_t) * (size_t)nhub));
+        HIP_TRY(hipMalloc((void**)&g->d_hubr, sizeof(int4) * (size_t)(nrec > 0 ? nrec : 1)));
+        launch_hub_ranks<OffT>(L, (const OffT*)g->off, g->n, thr, g->d_hub, nrec, (uint64_t*)mask.p,
+                               (uint32_t*)hbase.p, partial.p, g->d_hubid, g->d_hubr);
+        HIP_TRY(hipGetLastError());
+        g->nhub = (int)nhub;
+    }
     HIP_TRY(hipStreamSynchronize(s));
     return BFS_OK;
 }
@@ -844,6 +890,12 @@ bfs_status bfs_create_graph_csr(int64_t n, const void* d_offsets, int offset_byt
         }
     }
     g->persist_groups_max = g->off_bytes == 4 ? persist_max_groups<int32_t>() : persist_max_groups<int64_t>();
+    {
+        // hub-ranked probes pay off only when the frontier bitmap does not fit in L2
+        int l2 = 0;
+        if (hipDeviceGetAttribute(&l2, hipDeviceAttributeL2CacheSize, g->device) != hipSuccess) l2 = 0;
+        g->hub_auto = l2 > 0 && (n + 7) / 8 > (int64_t)l2;
+    }
     // only in a symmetric graph is a vertex without row entries unreachable
     if (n > 0 && (g->flags & BFS_GRAPH_SYMMETRIC)) {
         bfs_status bs = g->off_bytes == 4 ? build_derived<int32_t>(g, (hipStream_t)hip_stream)
@@ -925,6 +977,8 @@ void bfs_destroy_graph(bfs_graph* g) {
     if (g->d_iso) (void)hipFree(g->d_iso);
     if (g->d_head) (void)hipFree(g->d_head);
     if (g->d_hub) (void)hipFree(g->d_hub);
+    if (g->d_hubid) (void)hipFree(g->d_hubid);
+    if (g->d_hubr) (void)hipFree(g->d_hubr);
     if (g->d_nbase) (void)hipFree(g->d_nbase);
     if (g->h_buf) (void)hipHostFree(g->h_buf);
     delete g;

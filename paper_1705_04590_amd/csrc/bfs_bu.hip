@@ -48,16 +48,29 @@ __device__ __forceinline__ uint64_t stream_load(const uint64_t* p) { return __bu
 // frontier among them far more often (the frontier of that level is made of
 // high-degree vertices), so fewer probes are made; a miss then scans the whole
 // row from its start.
+//
+// HUB = 2 (any-parent searches on graphs with hub ranks): the head holds the
+// two neighbours of highest degree and, packed in its last word, their ranks
+// among the graph's hubs (0xFFFF: not a hub).  The frontier bits of all hubs
+// (HUB_BITS bits, gathered once per level into `hb`) are copied to LDS when
+// the workgroup starts, so a probe of a hub neighbour reads LDS, not the
+// frontier bitmap in memory.
 template <typename OffT, int HUB>
 __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
     const int4* __restrict__ head, const uint64_t* __restrict__ iso, const uint32_t* __restrict__ nbase,
     const OffT* __restrict__ off, const int32_t* __restrict__ cols,
-    const uint64_t* __restrict__ fbits, uint64_t* __restrict__ nbits, uint64_t* __restrict__ visited,
-    uint64_t* __restrict__ vprev, int32_t* __restrict__ parent, int32_t* __restrict__ depth, int64_t W, int GW,
+    const uint64_t* __restrict__ fbits, const uint64_t* __restrict__ hb, uint64_t* __restrict__ nbits,
+    uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev, int32_t* __restrict__ parent,
+    int32_t* __restrict__ depth, int64_t W, int GW,
     int32_t next_depth, int serial_len, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot) {
     __shared__ int32_t s_list[BU_BLOCK / WAVE][BU_WIN];
     __shared__ int32_t s_hidx[BU_BLOCK / WAVE][BU_WIN];
     __shared__ unsigned long long s_nb[BU_BLOCK / WAVE][WAVE];
+    __shared__ uint64_t s_hb[HUB == 2 ? HUB_BITS / 64 : 1];
+    if (HUB == 2) {
+        for (int i = threadIdx.x; i < HUB_BITS / 64; i += BU_BLOCK) s_hb[i] = hb[i];
+        __syncthreads();
+    }
     zero_slot(zslot);
     const int lane = lane_id();
     const int wid = threadIdx.x / WAVE;
@@ -120,15 +133,26 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
                 const int deg = act ? h.x : 0;
                 int32_t par = -1;
                 int32_t pos = 0;   // position of the hit in the row
-                if (deg > 0 && bit_of(fbits[h.y >> 6], h.y)) { par = h.y; pos = 0; }
-                else if (deg > 1 && bit_of(fbits[h.z >> 6], h.z)) { par = h.z; pos = 1; }
-                else if (deg > 2 && bit_of(fbits[h.w >> 6], h.w)) { par = h.w; pos = 2; }
+                // entries the head probes; with HUB = 2 its last word holds ranks
+                constexpr int32_t nprobe = HUB == 2 ? 2 : 3;
+                if (HUB == 2) {
+                    const uint32_t r0 = (uint32_t)h.w & 0xFFFFu, r1 = (uint32_t)h.w >> 16;
+                    // both probes are issued before either is tested
+                    const uint64_t f0 = deg > 0 ? (r0 != 0xFFFFu ? s_hb[r0 >> 6] : fbits[h.y >> 6]) : 0ull;
+                    const uint64_t f1 = deg > 1 ? (r1 != 0xFFFFu ? s_hb[r1 >> 6] : fbits[h.z >> 6]) : 0ull;
+                    if (deg > 0 && bit_of(f0, r0 != 0xFFFFu ? (int32_t)r0 : h.y)) { par = h.y; pos = 0; }
+                    else if (deg > 1 && bit_of(f1, r1 != 0xFFFFu ? (int32_t)r1 : h.z)) { par = h.z; pos = 1; }
+                } else {
+                    if (deg > 0 && bit_of(fbits[h.y >> 6], h.y)) { par = h.y; pos = 0; }
+                    else if (deg > 1 && bit_of(fbits[h.z >> 6], h.z)) { par = h.z; pos = 1; }
+                    else if (deg > 2 && bit_of(fbits[h.w >> 6], h.w)) { par = h.w; pos = 2; }
+                }
                 // continuation: positions relative to the row start (rows hold < 2^31 entries);
                 // `pos` counts the head probes too when the head is not a row prefix
-                constexpr int32_t skip = HUB ? 0 : 3, pbase = HUB ? 3 : 0;
+                constexpr int32_t skip = HUB ? 0 : 3, pbase = HUB ? nprobe : 0;
                 int64_t beg = 0;
                 int32_t rp = deg;   // next entry to scan; deg when nothing is left
-                if (par < 0 && deg > 3) {
+                if (par < 0 && deg > nprobe) {
                     beg = (int64_t)off[v];
                     const int32_t lim = deg - skip > serial_len ? skip + serial_len : deg;
                     const int32_t* row = cols + beg;
@@ -180,7 +204,7 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
                     }
                 }
                 if (par >= 0) found(v, par, pos, deg);
-                else if (act) my_x += (uint64_t)(deg > 3 ? pbase + deg : deg);
+                else if (act) my_x += (uint64_t)(deg > nprobe ? pbase + deg : deg);
             }
             wave_lds_sync();
         }
@@ -207,21 +231,20 @@ static int group_words(int64_t W, int waves) {
 }
 
 template <typename OffT>
-void launch_bu_sweep(const Launch& L, const int4* head, bool hub, const uint64_t* iso, const uint32_t* nbase,
-                     const OffT* off, const int32_t* cols, const uint64_t* fbits, uint64_t* nbits, uint64_t* visited,
-                     uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W, int32_t next_depth, int serial_len,
-                     uint64_t* slot, uint64_t* zslot) {
+void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t* iso, const uint32_t* nbase,
+                     const OffT* off, const int32_t* cols, const uint64_t* fbits, const uint64_t* hb, uint64_t* nbits,
+                     uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W,
+                     int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot) {
     const int gw = group_words(W, L.grid_cap * (BU_BLOCK / WAVE));
     const int64_t G = (W + gw - 1) / gw;
     const int g = grid_for(G, BU_BLOCK / WAVE, L.grid_cap);
-    if (hub)
-        hipLaunchKernelGGL((k_bu_sweep<OffT, 1>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off, cols,
-                           fbits, nbits,
-                           visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot, zslot);
-    else
-        hipLaunchKernelGGL((k_bu_sweep<OffT, 0>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off, cols,
-                           fbits, nbits,
-                           visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot, zslot);
+#define BFS_SWEEP(H)                                                                                          \
+    hipLaunchKernelGGL((k_bu_sweep<OffT, H>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off, cols, \
+                       fbits, hb, nbits, visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot, zslot)
+    if (hub == 2) BFS_SWEEP(2);
+    else if (hub == 1) BFS_SWEEP(1);
+    else BFS_SWEEP(0);
+#undef BFS_SWEEP
 }
 
 // ------------------------------------------------------------------ row heads
@@ -312,10 +335,125 @@ void launch_hub_heads(const Launch& L, const OffT* off, const int32_t* cols, int
                        iso, nbase, hub);
 }
 
+// ------------------------------------------------------------------ hub ranks
+// The hubs are the vertices of degree >= a threshold chosen so that at most
+// HUB_BITS - 1 of them exist; rank = position among the hubs in id order.
+// small degrees (most vertices) are counted in LDS first: same-address
+// global atomics would serialise
+constexpr int HIST_LDS = 2048;
+
+template <typename OffT>
+__global__ __launch_bounds__(256) void k_deg_hist(const OffT* __restrict__ off, int64_t n,
+                                                  uint32_t* __restrict__ hist, int nbins) {
+    __shared__ uint32_t s_h[HIST_LDS];
+    for (int i = threadIdx.x; i < HIST_LDS; i += blockDim.x) s_h[i] = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const int64_t d = (int64_t)off[v + 1] - (int64_t)off[v];
+        if (d <= 0) continue;
+        const int64_t b = d < nbins - 1 ? d : nbins - 1;
+        if (b < HIST_LDS) atomicAdd(&s_h[b], 1u);
+        else atomicAdd(&hist[b], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < HIST_LDS && i < nbins; i += blockDim.x)
+        if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+}
+
+template <typename OffT>
+__global__ void k_hub_mask(const OffT* __restrict__ off, int64_t n, int64_t W, int64_t thr,
+                           uint64_t* __restrict__ mask) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < W; w += stride) {
+        uint64_t m = 0;
+        for (int b = 0; b < 64; ++b) {
+            const int64_t v = w * 64 + b;
+            if (v < n && (int64_t)off[v + 1] - (int64_t)off[v] >= thr) m |= 1ull << b;
+        }
+        mask[w] = m;
+    }
+}
+
+struct PopcWord {
+    const uint64_t* m;
+    __device__ int64_t operator()(int64_t w) const { return __popcll(m[w]); }
+};
+
+__global__ void k_hub_ids(const uint64_t* __restrict__ mask, const uint32_t* __restrict__ hbase, int64_t W,
+                          int32_t* __restrict__ hubid) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < W; w += stride) {
+        uint64_t m = mask[w];
+        uint32_t r = hbase[w];
+        while (m) {
+            const int b = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            hubid[r++] = (int32_t)(w * 64 + b);
+        }
+    }
+}
+
+// {deg, c0, c1, ranks} from the hub heads {deg, c0, c1, c2}
+__global__ void k_hub_rank_heads(const int4* __restrict__ hub, int64_t nrec, const uint64_t* __restrict__ mask,
+                                 const uint32_t* __restrict__ hbase, int4* __restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nrec; i += stride) {
+        const int4 h = hub[i];
+        uint32_t rk[2] = {0xFFFFu, 0xFFFFu};
+        const int32_t c[2] = {h.y, h.z};
+        for (int j = 0; j < 2; ++j) {
+            if (c[j] < 0) continue;
+            const uint64_t mw = mask[c[j] >> 6];
+            const uint64_t bit = 1ull << (c[j] & 63);
+            if (mw & bit) rk[j] = hbase[c[j] >> 6] + (uint32_t)__popcll(mw & (bit - 1ull));
+        }
+        out[i] = make_int4(h.x, h.y, h.z, (int32_t)(rk[0] | (rk[1] << 16)));
+    }
+}
+
+template <typename OffT>
+void launch_deg_hist(const Launch& L, const OffT* off, int64_t n, uint32_t* hist, int nbins) {
+    hipLaunchKernelGGL(k_deg_hist<OffT>, dim3(grid_for(n, 256, 1024)), dim3(256), 0, L.stream, off, n, hist, nbins);
+}
+
+template <typename OffT>
+void launch_hub_ranks(const Launch& L, const OffT* off, int64_t n, int64_t thr, const int4* hub, int64_t nrec,
+                      uint64_t* mask, uint32_t* hbase, int64_t* partial, int32_t* hubid, int4* out) {
+    const int64_t W = (n + 63) / 64;
+    hipLaunchKernelGGL(k_hub_mask<OffT>, dim3(grid_for(W, 256, L.grid_cap)), dim3(256), 0, L.stream, off, n, W, thr,
+                       mask);
+    launch_scan(L.stream, PopcWord{mask}, (const uint64_t*)nullptr, W, partial, BaseSink{hbase});
+    hipLaunchKernelGGL(k_hub_ids, dim3(grid_for(W, 256, L.grid_cap)), dim3(256), 0, L.stream, mask, hbase, W, hubid);
+    hipLaunchKernelGGL(k_hub_rank_heads, dim3(grid_for(nrec, 256, L.grid_cap)), dim3(256), 0, L.stream, hub, nrec,
+                       mask, hbase, out);
+}
+
+// frontier bits of the hubs, in rank order (one wave per output word)
+__global__ void k_hub_gather(const uint64_t* __restrict__ fbits, const int32_t* __restrict__ hubid, int nhub,
+                             uint64_t* __restrict__ hb) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    bool on = false;
+    if (r < nhub) {
+        const int32_t v = hubid[r];
+        on = (fbits[v >> 6] >> (v & 63)) & 1ull;
+    }
+    const uint64_t m = __ballot(on);
+    if (lane_id() == 0 && r < HUB_BITS) hb[r >> 6] = m;
+}
+
+void launch_hub_gather(const Launch& L, const uint64_t* fbits, const int32_t* hubid, int nhub, uint64_t* hb) {
+    hipLaunchKernelGGL(k_hub_gather, dim3(HUB_BITS / 256), dim3(256), 0, L.stream, fbits, hubid, nhub, hb);
+}
+
 #define BFS_BU_INST(T)                                                                                           \
-    template void launch_bu_sweep<T>(const Launch&, const int4*, bool, const uint64_t*, const uint32_t*,         \
-                                     const T*, const int32_t*, const uint64_t*, uint64_t*, uint64_t*, uint64_t*, \
-                                     int32_t*, int32_t*, int64_t, int32_t, int, uint64_t*, uint64_t*);           \
+    template void launch_bu_sweep<T>(const Launch&, const int4*, int, const uint64_t*, const uint32_t*,          \
+                                     const T*, const int32_t*, const uint64_t*, const uint64_t*, uint64_t*,      \
+                                     uint64_t*, uint64_t*, int32_t*, int32_t*, int64_t, int32_t, int, uint64_t*, \
+                                     uint64_t*);                                                                 \
+    template void launch_deg_hist<T>(const Launch&, const T*, int64_t, uint32_t*, int);                          \
+    template void launch_hub_ranks<T>(const Launch&, const T*, int64_t, int64_t, const int4*, int64_t,          \
+                                      uint64_t*, uint32_t*, int64_t*, int32_t*, int4*);                         \
     template void launch_row_heads<T>(const Launch&, const T*, const int32_t*, int64_t, const uint64_t*,        \
                                       const uint32_t*, int4*);                                                   \
     template void launch_hub_heads<T>(const Launch&, const T*, const int32_t*, int64_t, const uint64_t*,        \

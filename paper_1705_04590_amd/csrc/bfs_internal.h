@@ -18,6 +18,8 @@ constexpr int WAVE = 64;
 constexpr int TD_BLOCK = 256;                 // threads per top-down expand workgroup
 constexpr int TD_EPT = 4;                     // edges per thread per tile
 constexpr int TD_TILE = TD_BLOCK * TD_EPT;    // edges per tile
+constexpr int HUB_BITS = 65536;               // hub ranks 0..HUB_BITS-2; HUB_BITS-1 marks "not a hub"
+constexpr int HUB_HIST_BINS = 1 << 20;        // degree histogram for the hub threshold
 constexpr int SCAN_BLOCK = 1024;              // threads per scan workgroup
 constexpr int SCAN_IPT = 4;                   // items per scan thread
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_IPT;
@@ -77,11 +79,24 @@ void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t*
                       uint64_t* visited, uint64_t* claim, int32_t* qnext, uint64_t* slot, uint64_t* zslot,
                       int32_t next_depth);
 
+// head kinds (hub): 0 row heads, 1 hub heads, 2 hub heads with hub ranks
+// (then hb holds the hubs' frontier bits, HUB_BITS bits)
 template <typename OffT>
-void launch_bu_sweep(const Launch& L, const int4* head, bool hub, const uint64_t* iso, const uint32_t* nbase,
-                     const OffT* off, const int32_t* cols, const uint64_t* fbits, uint64_t* nbits, uint64_t* visited,
-                     uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W, int32_t next_depth, int serial_len,
-                     uint64_t* slot, uint64_t* zslot);
+void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t* iso, const uint32_t* nbase,
+                     const OffT* off, const int32_t* cols, const uint64_t* fbits, const uint64_t* hb, uint64_t* nbits,
+                     uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W,
+                     int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot);
+// Hub ranks: hist[min(deg, nbins-1)] counts the vertices with edges; the hubs
+// are the vertices of degree >= thr (fewer than HUB_BITS); mask (W words),
+// hbase (W) and partial (scan scratch) are temporaries; hubid receives the
+// hubs in id order and out the rank heads {deg, c0, c1, rank(c0) | rank(c1) << 16}.
+template <typename OffT>
+void launch_deg_hist(const Launch& L, const OffT* off, int64_t n, uint32_t* hist, int nbins);
+template <typename OffT>
+void launch_hub_ranks(const Launch& L, const OffT* off, int64_t n, int64_t thr, const int4* hub, int64_t nrec,
+                      uint64_t* mask, uint32_t* hbase, int64_t* partial, int32_t* hubid, int4* out);
+// hb[r / 64] bit r%64 = frontier bit of hub r (all HUB_BITS bits written)
+void launch_hub_gather(const Launch& L, const uint64_t* fbits, const int32_t* hubid, int nhub, uint64_t* hb);
 // Head records exist for the vertices with edges only, stored by rank among
 // them: record of v = nbase[v/64] + (vertices with edges before v in its word).
 // nbase (W entries) from the isolated-vertex bitmap; partial: scan scratch

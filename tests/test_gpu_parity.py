@@ -119,7 +119,9 @@ def test_parity_all_modes(orc, graphs, name, direction):
         for s in sources_for(dg.off):
             ref = orc.bfs_min(dg.off, dg.cols, int(s))
             for pm, claim, head in ((bfs.BFS_PARENT_ANY, 0, 0), (bfs.BFS_PARENT_ANY, 1, 0),
-                                    (bfs.BFS_PARENT_ANY, 0, 1), (bfs.BFS_PARENT_MIN, 0, 0)):
+                                    (bfs.BFS_PARENT_ANY, 0, 1), (bfs.BFS_PARENT_ANY, 0, 2),
+                                    (bfs.BFS_PARENT_ANY, 0, 3), (bfs.BFS_PARENT_MIN, 0, 0),
+                                    (bfs.BFS_PARENT_MIN, 0, 3)):
                 p, d, st = dg.run(s, dir=dirv, parent_mode=pm, td_claim=claim, bu_head=head)
                 check(orc, dg, s, p, d, pm == bfs.BFS_PARENT_MIN, ref)
                 assert st.reached == int((d >= 0).sum())
@@ -161,6 +163,10 @@ def test_config1_scale16_int32_offsets(orc, graphs):
             for pm in (bfs.BFS_PARENT_ANY, bfs.BFS_PARENT_MIN):
                 p, d, _ = dg.run(s, dir=dirv, parent_mode=pm)
                 check(orc, dg, s, p, d, pm == bfs.BFS_PARENT_MIN, ref)
+        # hub-rank heads: some neighbours are hubs (LDS bits), others are not
+        for head in (2, 3):
+            p, d, _ = dg.run(s, parent_mode=bfs.BFS_PARENT_ANY, bu_head=head)
+            check(orc, dg, s, p, d, False, ref)
 
 
 def test_tuning_knobs_do_not_change_results(orc, graphs):
@@ -261,8 +267,9 @@ def test_config2_scale22_sampled_sources(orc):
     srcs = graphgen.random_sources(off, 64, seed=2)
     for s in srcs[:3]:
         ref = orc.bfs_min(off, cols, int(s))
-        for pm in (bfs.BFS_PARENT_ANY, bfs.BFS_PARENT_MIN):
-            p, d, _ = dg.run(s, parent_mode=pm)
+        for pm, head in ((bfs.BFS_PARENT_ANY, 0), (bfs.BFS_PARENT_ANY, 2), (bfs.BFS_PARENT_ANY, 3),
+                         (bfs.BFS_PARENT_MIN, 0)):
+            p, d, _ = dg.run(s, parent_mode=pm, bu_head=head)
             check(orc, dg, s, p, d, pm == bfs.BFS_PARENT_MIN, ref)
 
 
