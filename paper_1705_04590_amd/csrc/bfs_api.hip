@@ -518,7 +518,6 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             }
             const bool from_td = fmt_queue;   // the previous level ran top-down
             fmt_queue = false;
-            HIP_TRY(T.begin(BFS_K_BU_SWEEP));
             // any-parent searches probe the highest-degree neighbours first.
             // On a bottom-up level entered from top-down (small frontier, many
             // misses) of a graph whose frontier bitmap exceeds the L2, the two
@@ -528,7 +527,14 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             const bool ranked = g->nhub > 0 && (o.bu_head == 3 || (o.bu_head == 0 && from_td && g->hub_auto));
             const int hk = claim_mode == CLAIM_MIN || o.bu_head == 1 ? 0 : ranked ? 2 : 1;
             uint64_t* hb = (uint64_t*)(ws + Lo.hb);
-            if (hk == 2) launch_hub_gather(L, fbits, g->d_hubid, g->nhub, hb);
+            if (hk == 2) {
+                HIP_TRY(T.begin(BFS_K_CONVERT));
+                launch_hub_gather(L, fbits, g->d_hubid, g->nhub, hb);
+                HIP_TRY(hipGetLastError());
+                HIP_TRY(T.end(BFS_K_CONVERT, level));
+                if (st) st->launches[BFS_K_CONVERT] += 1;
+            }
+            HIP_TRY(T.begin(BFS_K_BU_SWEEP));
             launch_bu_sweep<OffT>(L, hk == 2 ? g->d_hubr : hk == 1 ? g->d_hub : g->d_head, hk, g->d_iso, g->d_nbase,
                                   off, g->cols, fbits, hb, nbits, visited, vprev, parent, depth, W, next_depth, serial,
                                   slot, zslot);
