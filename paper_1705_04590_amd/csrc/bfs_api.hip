@@ -361,9 +361,15 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     }
     const int64_t deg_s = (int64_t)ctx->mbox[2] - (int64_t)ctx->mbox[1];
 
+    // ANY parents with fetch-or claims never read parent/depth, so their -1
+    // fill moves into the first bottom-up sweep (whole lines, once), or to a
+    // fill pass at the end when no bottom-up level runs; the other claim
+    // modes compare against -1 and need it before the first top-down level
+    const bool lazy_out = claim_mode == CLAIM_BITMAP && o.dir != BFS_DIR_TD && g->d_iso != nullptr;
+    bool out_filled = !lazy_out;
     HIP_TRY(T.begin(BFS_K_INIT));
     launch_init(L, parent, depth, n, visited, vprev, fbits, claim, g->d_iso, W, qcur, src, counters,
-                (int64_t)((Lo.ctl_end - Lo.counters) / sizeof(uint64_t)));
+                (int64_t)((Lo.ctl_end - Lo.counters) / sizeof(uint64_t)), !lazy_out);
     HIP_TRY(hipGetLastError());
     HIP_TRY(T.end(BFS_K_INIT, -1));
     if (st) st->launches[BFS_K_INIT] += 1;
@@ -537,7 +543,8 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             HIP_TRY(T.begin(BFS_K_BU_SWEEP));
             launch_bu_sweep<OffT>(L, hk == 2 ? g->d_hubr : hk == 1 ? g->d_hub : g->d_head, hk, g->d_iso, g->d_nbase,
                                   off, g->cols, fbits, hb, nbits, visited, vprev, parent, depth, W, next_depth, serial,
-                                  slot, zslot);
+                                  slot, zslot, !out_filled, n, src);
+            out_filled = true;
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_BU_SWEEP, level));
             if (st) st->launches[BFS_K_BU_SWEEP] += 1;
@@ -576,6 +583,13 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             uint64_t* t = fbits; fbits = nbits; nbits = t;
         }
         if (level > n + 1) return fail(BFS_E_HIP, "level loop did not terminate");
+    }
+    if (!out_filled) {
+        HIP_TRY(T.begin(BFS_K_INIT));
+        launch_fill_unreached(L, parent, depth, n, visited, g->d_iso, src);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(T.end(BFS_K_INIT, -1));
+        if (st) st->launches[BFS_K_INIT] += 1;
     }
     if (st) {
         st->levels = level;

@@ -55,14 +55,20 @@ __device__ __forceinline__ uint64_t stream_load(const uint64_t* p) { return __bu
 // (HUB_BITS bits, gathered once per level into `hb`) are copied to LDS when
 // the workgroup starts, so a probe of a hub neighbour reads LDS, not the
 // frontier bitmap in memory.
-template <typename OffT, int HUB>
+//
+// FILL = 1 (first bottom-up level of a search whose outputs were left
+// uninitialised): after each group, the entries of its isolated and still
+// unreached vertices get -1, 64 consecutive entries per store, so together
+// with the hits every line of the outputs is written once on this level.
+template <typename OffT, int HUB, int FILL>
 __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
     const int4* __restrict__ head, const uint64_t* __restrict__ iso, const uint32_t* __restrict__ nbase,
     const OffT* __restrict__ off, const int32_t* __restrict__ cols,
     const uint64_t* __restrict__ fbits, const uint64_t* __restrict__ hb, uint64_t* __restrict__ nbits,
     uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev, int32_t* __restrict__ parent,
     int32_t* __restrict__ depth, int64_t W, int GW,
-    int32_t next_depth, int serial_len, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot) {
+    int32_t next_depth, int serial_len, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot, int64_t n,
+    int64_t src) {
     __shared__ int32_t s_list[BU_BLOCK / WAVE][BU_WIN];
     __shared__ int32_t s_hidx[BU_BLOCK / WAVE][BU_WIN];
     __shared__ unsigned long long s_nb[BU_BLOCK / WAVE][WAVE];
@@ -216,6 +222,24 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
                 vprev[w] = wv | nb;
             }
         }
+        if (FILL) {
+            // isolated (not hasrow) or unvisited and not found now; ids >= n
+            // and the source excluded
+            uint64_t neg = 0;
+            if (mine) {
+                neg = ~hasrow | (~wv & ~nb);
+                if (w == W - 1 && (n & 63)) neg &= (1ull << (n & 63)) - 1ull;
+                if (w == (src >> 6)) neg &= ~(1ull << (src & 63));
+            }
+            for (int j = 0; j < GW; ++j) {
+                const uint64_t m = __shfl(neg, j, WAVE);
+                if ((m >> lane) & 1ull) {
+                    const int64_t v = (w0 + j) * WAVE + lane;
+                    parent[v] = -1;
+                    depth[v] = -1;
+                }
+            }
+        }
         wave_lds_sync();
     }
     uint64_t* ln = slot_line(slot);
@@ -234,16 +258,24 @@ template <typename OffT>
 void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t* iso, const uint32_t* nbase,
                      const OffT* off, const int32_t* cols, const uint64_t* fbits, const uint64_t* hb, uint64_t* nbits,
                      uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W,
-                     int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot) {
+                     int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot, bool fill, int64_t n,
+                     int64_t src) {
     const int gw = group_words(W, L.grid_cap * (BU_BLOCK / WAVE));
     const int64_t G = (W + gw - 1) / gw;
     const int g = grid_for(G, BU_BLOCK / WAVE, L.grid_cap);
-#define BFS_SWEEP(H)                                                                                          \
-    hipLaunchKernelGGL((k_bu_sweep<OffT, H>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off, cols, \
-                       fbits, hb, nbits, visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot, zslot)
-    if (hub == 2) BFS_SWEEP(2);
-    else if (hub == 1) BFS_SWEEP(1);
-    else BFS_SWEEP(0);
+#define BFS_SWEEP(H, F)                                                                                          \
+    hipLaunchKernelGGL((k_bu_sweep<OffT, H, F>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off, cols, \
+                       fbits, hb, nbits, visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot, zslot, n, \
+                       src)
+    if (fill) {
+        if (hub == 2) BFS_SWEEP(2, 1);
+        else if (hub == 1) BFS_SWEEP(1, 1);
+        else BFS_SWEEP(0, 1);
+    } else {
+        if (hub == 2) BFS_SWEEP(2, 0);
+        else if (hub == 1) BFS_SWEEP(1, 0);
+        else BFS_SWEEP(0, 0);
+    }
 #undef BFS_SWEEP
 }
 
@@ -450,7 +482,7 @@ void launch_hub_gather(const Launch& L, const uint64_t* fbits, const int32_t* hu
     template void launch_bu_sweep<T>(const Launch&, const int4*, int, const uint64_t*, const uint32_t*,          \
                                      const T*, const int32_t*, const uint64_t*, const uint64_t*, uint64_t*,      \
                                      uint64_t*, uint64_t*, int32_t*, int32_t*, int64_t, int32_t, int, uint64_t*, \
-                                     uint64_t*);                                                                 \
+                                     uint64_t*, bool, int64_t, int64_t);                                         \
     template void launch_deg_hist<T>(const Launch&, const T*, int64_t, uint32_t*, int);                          \
     template void launch_hub_ranks<T>(const Launch&, const T*, int64_t, int64_t, const int4*, int64_t,          \
                                       uint64_t*, uint32_t*, int64_t*, int32_t*, int4*);                         \

@@ -60,7 +60,10 @@ void launch_isolated_mask(const Launch& L, const OffT* off, int64_t n, int64_t W
 
 void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, uint64_t* visited, uint64_t* vprev,
                  uint64_t* fbits, uint64_t* claim, const uint64_t* iso, int64_t W, int32_t* queue, int64_t src,
-                 uint64_t* counters, int64_t counter_words);
+                 uint64_t* counters, int64_t counter_words, bool write_out);
+// parent = depth = -1 for every vertex not reached (the source excepted)
+void launch_fill_unreached(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, const uint64_t* visited,
+                           const uint64_t* iso, int64_t src);
 
 // degree prefix sum of the frontier queue + tile partition for the expand
 // (scan[i] = sum of degrees of q[0..i), tile_start[t] = queue index owning
@@ -80,12 +83,15 @@ void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t*
                       int32_t next_depth);
 
 // head kinds (hub): 0 row heads, 1 hub heads, 2 hub heads with hub ranks
-// (then hb holds the hubs' frontier bits, HUB_BITS bits)
+// (then hb holds the hubs' frontier bits, HUB_BITS bits).  fill: the outputs
+// were not initialised; the sweep also writes -1 to every entry of the
+// unreached and isolated vertices (the source, of id src, excepted)
 template <typename OffT>
 void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t* iso, const uint32_t* nbase,
                      const OffT* off, const int32_t* cols, const uint64_t* fbits, const uint64_t* hb, uint64_t* nbits,
                      uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W,
-                     int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot);
+                     int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot, bool fill, int64_t n,
+                     int64_t src);
 // Hub ranks: hist[min(deg, nbins-1)] counts the vertices with edges; the hubs
 // are the vertices of degree >= thr (fewer than HUB_BITS); mask (W words),
 // hbase (W) and partial (scan scratch) are temporaries; hubid receives the

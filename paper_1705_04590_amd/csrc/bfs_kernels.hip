@@ -61,15 +61,22 @@ __global__ void k_init(int32_t* __restrict__ parent, int32_t* __restrict__ depth
                        uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev, uint64_t* __restrict__ fbits,
                        uint64_t* __restrict__ claim, const uint64_t* __restrict__ iso, int64_t W,
                        int32_t* __restrict__ queue, int64_t src, uint64_t* __restrict__ counters,
-                       int64_t counter_words) {
-    // every output entry is written here, whole lines at a time; the search
-    // then overwrites the reached ones
+                       int64_t counter_words, int write_out) {
+    // with write_out every output entry is written here, whole lines at a
+    // time, and the search overwrites the reached ones; otherwise only the
+    // source's entries are, and the first bottom-up level (or the final fill)
+    // writes the rest
     int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = tid; v < n; v += stride) {
-        bool s = v == src;
-        parent[v] = s ? (int32_t)src : -1;
-        depth[v] = s ? 0 : -1;
+    if (write_out) {
+        for (int64_t v = tid; v < n; v += stride) {
+            bool s = v == src;
+            parent[v] = s ? (int32_t)src : -1;
+            depth[v] = s ? 0 : -1;
+        }
+    } else if (tid == 0) {
+        parent[src] = (int32_t)src;
+        depth[src] = 0;
     }
     for (int64_t w = tid; w < W; w += stride) {
         // vertices without edges can never be reached: they start visited, and
@@ -88,10 +95,32 @@ __global__ void k_init(int32_t* __restrict__ parent, int32_t* __restrict__ depth
 
 void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, uint64_t* visited, uint64_t* vprev,
                  uint64_t* fbits, uint64_t* claim, const uint64_t* iso, int64_t W, int32_t* queue, int64_t src,
-                 uint64_t* counters, int64_t counter_words) {
-    int g = grid_for(n > W ? n : W, 256, L.grid_cap * 4);
+                 uint64_t* counters, int64_t counter_words, bool write_out) {
+    int g = grid_for(write_out && n > W ? n : W, 256, L.grid_cap * 4);
     hipLaunchKernelGGL(k_init, dim3(g), dim3(256), 0, L.stream, parent, depth, n, visited, vprev, fbits, claim, iso,
-                       W, queue, src, counters, counter_words);
+                       W, queue, src, counters, counter_words, write_out ? 1 : 0);
+}
+
+// -1 for every vertex the search did not reach (unvisited, or without edges),
+// the source excepted: the end of a search whose outputs were not initialised
+// and that ran no bottom-up level
+__global__ void k_fill_unreached(int32_t* __restrict__ parent, int32_t* __restrict__ depth, int64_t n,
+                                 const uint64_t* __restrict__ visited, const uint64_t* __restrict__ iso, int64_t src) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const uint64_t bit = 1ull << (v & 63);
+        const bool reached = (visited[v >> 6] & bit) && !(iso && (iso[v >> 6] & bit));
+        if (!reached && v != src) {
+            parent[v] = -1;
+            depth[v] = -1;
+        }
+    }
+}
+
+void launch_fill_unreached(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, const uint64_t* visited,
+                           const uint64_t* iso, int64_t src) {
+    hipLaunchKernelGGL(k_fill_unreached, dim3(grid_for(n, 256, L.grid_cap * 4)), dim3(256), 0, L.stream, parent, depth,
+                       n, visited, iso, src);
 }
 
 // ------------------------------------------------------------------ host mailbox

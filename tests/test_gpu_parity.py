@@ -34,6 +34,9 @@ class DevGraph:
         self.depth = torch.empty(max(self.n, 1), dtype=torch.int32, device=DEV)
 
     def run(self, s, **kw):
+        # poison the outputs: every entry must be written by the call itself
+        self.parent.fill_(-7)
+        self.depth.fill_(-7)
         st = bfs.bfs_run(self.g, int(s), self.parent, self.depth, self.ws, bfs.bfs_opts_default(**kw))
         torch.cuda.synchronize()
         return self.parent[: self.n].cpu().numpy(), self.depth[: self.n].cpu().numpy(), st
@@ -177,6 +180,24 @@ def test_tuning_knobs_do_not_change_results(orc, graphs):
         for grid in (1, 7, 64, 4096):
             p, d, _ = dg.run(s, parent_mode=bfs.BFS_PARENT_MIN, bu_serial=serial, grid_blocks=grid)
             check(orc, dg, s, p, d, True, ref)
+
+
+@pytest.mark.parametrize("name", ["kron12", "pieces", "grid", "path"])
+def test_outputs_fully_written(orc, graphs, name):
+    """Every parent/depth entry is written by the call, whatever the level
+    schedule: searches with and without bottom-up levels, isolated sources,
+    the default any-parent mode (whose -1 fill happens inside the first
+    bottom-up sweep or in a final pass) and the modes that initialise first."""
+    for off_dtype in (np.int32, np.int64):
+        dg = get(graphs, name, off_dtype)
+        for s in sources_for(dg.off, k=2, seed=31):
+            ref = orc.bfs_min(dg.off, dg.cols, int(s))
+            for kw in (dict(), dict(dir=bfs.BFS_DIR_BU), dict(dir=bfs.BFS_DIR_TD), dict(alpha=1e-9),
+                       dict(alpha=1e9, beta=1e9), dict(small_edges=-1), dict(td_claim=1),
+                       dict(parent_mode=bfs.BFS_PARENT_MIN)):
+                p, d, _ = dg.run(s, **kw)
+                check(orc, dg, s, p, d, kw.get("parent_mode") == bfs.BFS_PARENT_MIN, ref)
+                assert (p >= -1).all() and (d >= -1).all()
 
 
 def test_repeat_runs_identical(graphs):
