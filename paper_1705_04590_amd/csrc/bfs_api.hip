@@ -393,15 +393,37 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     int64_t* d_rec = (int64_t*)(ws + Lo.rec);
     int level = 0;
     int64_t reached = 1, examined = 0;
+    bool same_level = false;   // retrying this level: its direction is already chosen
+    bool skip_engine = false;  // ... and it goes through the per-level kernels
     for (;;) {
         // ---- direction for this level (Section 4.4)
-        if (o.dir == BFS_DIR_TD) cur_dir = 0;
+        if (same_level) same_level = false;
+        else if (o.dir == BFS_DIR_TD) cur_dir = 0;
         else if (o.dir == BFS_DIR_BU) cur_dir = 1;
         else if (cur_dir == 0) { if ((double)m_f * o.alpha > (double)m_u) cur_dir = 1; }
         else { if ((double)n_f * o.beta < (double)n) cur_dir = 0; }
 
+        if (cur_dir == 0 && !fmt_queue) {
+            uint64_t* cslot = counters + (size_t)(level % SLOTS) * SLOT_WORDS;
+            // bottom-up -> top-down: the frontier bitmap becomes a queue in
+            // vertex order.  Its length is n_f exactly (the sweep counted one
+            // per bit it set), so the host knows it and the persistent engine
+            // may take the following small levels; the device copy goes to
+            // slot word 4.
+            HIP_TRY(T.begin(BFS_K_CONVERT));
+            const int nl = launch_bitmap_to_queue(L, fbits, W, qcur, cslot + 4, partial);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(T.end(BFS_K_CONVERT, level));
+            if (st) st->launches[BFS_K_CONVERT] += nl;
+            qlen_dev = nullptr;
+            qlen = n_f;
+            fmt_queue = true;
+        }
+
+        const bool engine_ok = engine_on && !skip_engine;
+        skip_engine = false;
         // ---- small top-down levels: run them back to back on the device
-        if (cur_dir == 0 && fmt_queue && !qlen_dev && m_f > 0 && engine_on && m_f <= cap_multi) {
+        if (cur_dir == 0 && fmt_queue && !qlen_dev && m_f > 0 && engine_ok && m_f <= cap_multi) {
             // one workgroup while the frontier is tiny, many once it grows
             const bool multi = m_f > cap_one;
             const int groups = multi ? pgroups : 1;
@@ -439,6 +461,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                 // the workgroups could not all be resident at once (a busy
                 // device): nothing was touched, continue level by level
                 engine_on = false;
+                same_level = true;
                 continue;
             }
             if (hs.reason == ENG_TIMEOUT) return fail(BFS_E_HIP, "top-down engine: grid barrier timed out");
@@ -469,23 +492,17 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             m_f = hs.m_f;
             m_u = hs.m_u;
             if (level > n + 1) return fail(BFS_E_HIP, "level loop did not terminate");
+            if (hs.levels_done == 0) {
+                // nothing ran (a cap hit at entry): this level, in the
+                // direction already chosen, goes through the per-level kernels
+                same_level = true;
+                skip_engine = true;
+            }
             continue;   // the host decides the next level
         }
 
         uint64_t* slot = counters + (size_t)(level % SLOTS) * SLOT_WORDS;
         uint64_t* zslot = counters + (size_t)((level + 1) % SLOTS) * SLOT_WORDS;
-        if (cur_dir == 0 && !fmt_queue) {
-            // bottom-up -> top-down: the frontier bitmap becomes a queue; its
-            // length stays on the device (slot word 4, cleared with the slot)
-            HIP_TRY(T.begin(BFS_K_CONVERT));
-            launch_bitmap_to_queue(L, fbits, W, qcur, slot + 4);
-            HIP_TRY(hipGetLastError());
-            HIP_TRY(T.end(BFS_K_CONVERT, level));
-            if (st) st->launches[BFS_K_CONVERT] += 1;
-            qlen_dev = slot + 4;
-            qlen = n_f;
-            fmt_queue = true;
-        }
 
         const int32_t next_depth = level + 1;
         if (cur_dir == 0) {

@@ -151,7 +151,10 @@ void launch_td_persist(const Launch& L, int mode, int groups, const OffT* off, c
                        int32_t* depth, uint64_t* visited, uint64_t* vprev, uint64_t* claim, int32_t* qa, int32_t* qb,
                        int64_t n, SmallIn in, SmallState* st, uint64_t* ctr, PersistCtl* ctl, int64_t* rec,
                        int rec_cap, double alpha, int64_t edge_cap, int64_t shrink_below, int64_t max_levels);
-void launch_bitmap_to_queue(const Launch& L, const uint64_t* bits, int64_t W, int32_t* q, uint64_t* qlen_ctr);
+// queue = set bits of `bits` in ascending order, *qlen_ctr = their count;
+// partial: scan scratch of ceil(W / SCAN_TILE) + 2 int64.  Returns launches.
+int launch_bitmap_to_queue(const Launch& L, const uint64_t* bits, int64_t W, int32_t* q, uint64_t* qlen_ctr,
+                           int64_t* partial);
 void launch_merge(const Launch& L, bool min_mode, uint64_t* visited, uint64_t* vprev, uint64_t* claim,
                   uint64_t* fnext, int64_t W);
 

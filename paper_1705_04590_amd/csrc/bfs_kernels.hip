@@ -322,39 +322,33 @@ void launch_clear_words(const Launch& L, uint64_t* w, int64_t nw) {
     hipLaunchKernelGGL(k_clear_words, dim3(grid_for(nw, 256, L.grid_cap * 4)), dim3(256), 0, L.stream, w, nw);
 }
 
-// one word per thread; workgroup-wide exclusive scan of popcounts gives each
-// thread its output position, one global atomicAdd per workgroup iteration
-__global__ __launch_bounds__(256) void k_bitmap_to_queue(const uint64_t* __restrict__ bits, int64_t W,
-                                                         int32_t* __restrict__ q, uint64_t* __restrict__ qlen_ctr) {
-    __shared__ int wsum[256 / WAVE];
-    __shared__ uint64_t s_base;
-    for (int64_t w0 = (int64_t)blockIdx.x * 256; w0 < W; w0 += (int64_t)gridDim.x * 256) {
-        const int64_t w = w0 + threadIdx.x;
-        uint64_t x = (w < W) ? bits[w] : 0ull;
-        int c = __popcll(x);
-        int inc = wave_incl_scan(c);
-        int wid = threadIdx.x / WAVE;
-        if (lane_id() == WAVE - 1) wsum[wid] = inc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int tot = 0;
-            for (int i = 0; i < 256 / WAVE; ++i) { int t = wsum[i]; wsum[i] = tot; tot += t; }
-            s_base = tot ? atomicAdd((unsigned long long*)qlen_ctr, (unsigned long long)tot) : 0;
-        }
-        __syncthreads();
-        int64_t pos = (int64_t)s_base + wsum[wid] + inc - c;
+// frontier bitmap -> queue in vertex order: a prefix sum of the words'
+// popcounts gives each word its output position (no shared counter, whose
+// same-address atomics would serialise), and the last item stores the length
+struct WordBits {
+    const uint64_t* b;
+    __device__ int64_t operator()(int64_t w) const { return __popcll(b[w]); }
+};
+struct BitsToQueue {
+    const uint64_t* b;
+    int32_t* q;
+    uint64_t* qlen;
+    __device__ void item(int64_t w, int64_t before, int64_t c) const {
+        if (!c) return;
+        uint64_t x = b[w];
+        int64_t p = before;
         while (x) {
-            int b = __ffsll((unsigned long long)x) - 1;
+            const int bb = __ffsll((unsigned long long)x) - 1;
             x &= x - 1;
-            q[pos++] = (int32_t)(w * 64 + b);
+            q[p++] = (int32_t)(w * 64 + bb);
         }
-        __syncthreads();
     }
-}
+    __device__ void last(int64_t, int64_t total) const { *qlen = (uint64_t)total; }
+};
 
-void launch_bitmap_to_queue(const Launch& L, const uint64_t* bits, int64_t W, int32_t* q, uint64_t* qlen_ctr) {
-    hipLaunchKernelGGL(k_bitmap_to_queue, dim3(grid_for(W, 256, L.grid_cap)), dim3(256), 0, L.stream, bits, W, q,
-                       qlen_ctr);
+int launch_bitmap_to_queue(const Launch& L, const uint64_t* bits, int64_t W, int32_t* q, uint64_t* qlen_ctr,
+                           int64_t* partial) {
+    return launch_scan(L.stream, WordBits{bits}, (const uint64_t*)nullptr, W, partial, BitsToQueue{bits, q, qlen_ctr});
 }
 
 // after a top-down level the bits that became set are the next frontier.

@@ -367,22 +367,42 @@ __global__ __launch_bounds__(256) void k_ms_bu_sweep(const OffT* __restrict__ of
     or_reduce_add(cn, cm, cor, cfull, cx, slot);
 }
 
-// vertices with a non-zero mask -> queue (bottom-up -> top-down)
+// vertices with a non-zero mask -> queue (bottom-up -> top-down).  Each
+// workgroup takes chunks of MQ_CHUNK vertices: it counts them, reserves its
+// range with one atomic per chunk (one per wave would serialise on the shared
+// counter), then writes them in vertex order within the chunk.
+constexpr int MQ_STEPS = 16;
+constexpr int MQ_CHUNK = 256 * MQ_STEPS;
+
 __global__ __launch_bounds__(256) void k_ms_mask_to_queue(const uint64_t* __restrict__ N, int64_t n,
                                                           int32_t* __restrict__ q, uint64_t* __restrict__ qlen) {
+    __shared__ int s_cnt[MQ_STEPS][256 / WAVE];
+    __shared__ uint64_t s_base;
     const int lane = lane_id();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n; v0 += stride) {
-        const int64_t v = v0 + threadIdx.x;
-        const bool on = v < n && N[v] != 0;
-        const uint64_t m = __ballot(on);
-        if (m) {
-            const int leader = __ffsll((unsigned long long)m) - 1;
-            uint64_t b = 0;
-            if (lane == leader) b = atomicAdd((unsigned long long*)qlen, (unsigned long long)__popcll(m));
-            b = __shfl(b, leader, WAVE);
-            if (on) q[b + __popcll(m & lanemask_lt())] = (int32_t)v;
+    const int wid = threadIdx.x / WAVE;
+    for (int64_t c0 = (int64_t)blockIdx.x * MQ_CHUNK; c0 < n; c0 += (int64_t)gridDim.x * MQ_CHUNK) {
+        uint64_t on_bits[MQ_STEPS];
+        for (int j = 0; j < MQ_STEPS; ++j) {
+            const int64_t v = c0 + (int64_t)j * 256 + threadIdx.x;
+            const uint64_t m = __ballot(v < n && N[v] != 0);
+            on_bits[j] = m;
+            if (lane == 0) s_cnt[j][wid] = __popcll(m);
         }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            // exclusive prefix over (step, wave) in vertex order
+            int tot = 0;
+            for (int j = 0; j < MQ_STEPS; ++j)
+                for (int i = 0; i < 256 / WAVE; ++i) { const int t = s_cnt[j][i]; s_cnt[j][i] = tot; tot += t; }
+            s_base = tot ? atomicAdd((unsigned long long*)qlen, (unsigned long long)tot) : 0;
+        }
+        __syncthreads();
+        for (int j = 0; j < MQ_STEPS; ++j) {
+            const uint64_t m = on_bits[j];
+            if ((m >> lane) & 1ull)
+                q[s_base + s_cnt[j][wid] + __popcll(m & lanemask_lt())] = (int32_t)(c0 + (int64_t)j * 256 + threadIdx.x);
+        }
+        __syncthreads();
     }
 }
 
@@ -559,7 +579,8 @@ void launch_ms_bu(const Launch& L, const OffT* off, const int32_t* cols, int64_t
 }
 
 void launch_ms_mask_to_queue(const Launch& L, const uint64_t* N, int64_t n, int32_t* q, uint64_t* qlen) {
-    hipLaunchKernelGGL(k_ms_mask_to_queue, dim3(grid_for(n, 256, L.grid_cap)), dim3(256), 0, L.stream, N, n, q, qlen);
+    hipLaunchKernelGGL(k_ms_mask_to_queue, dim3(grid_for(n, MQ_CHUNK, L.grid_cap)), dim3(256), 0, L.stream, N, n, q,
+                       qlen);
 }
 
 void launch_ms_clear_queue(const Launch& L, const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host,

@@ -156,7 +156,8 @@ __global__ __launch_bounds__(PT_BLOCK) void k_td_persist(
 
     for (;;) {
         if (done >= max_levels) { reason = ENG_LEVEL_CAP; break; }
-        if ((double)m_f * alpha > (double)m_u) { reason = ENG_TO_BU; break; }
+        // the host chose top-down for the first level; the rule decides the rest
+        if (done > 0 && (double)m_f * alpha > (double)m_u) { reason = ENG_TO_BU; break; }
         if (m_f > edge_cap) { reason = ENG_EDGE_CAP; break; }
         if (m_f < shrink_below) { reason = ENG_SHRINK; break; }
         uint64_t* slot = ctr + (size_t)(done % SLOTS) * SLOT_WORDS;
