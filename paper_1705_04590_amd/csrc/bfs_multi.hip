@@ -214,15 +214,28 @@ __device__ __forceinline__ uint64_t first_suppliers(const int32_t* __restrict__ 
     uint64_t found = 0;
     int64_t p = beg;
     const int64_t lim = (end - beg > serial) ? beg + serial : end;
+    // four entries per step: their column loads, then their mask loads, all
+    // independent; then taken in row order, stopping right after the entry
+    // that supplies the last needed source
     while (need && p < lim) {
-        const int32_t u = cols[p];
-        const uint64_t x = F[u] & need;
-        if (x) {
-            record(par_vm, lvl_vm, v, x, u, level);
-            found |= x;
-            need &= ~x;
+        int32_t u[4];
+        uint64_t f[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) u[j] = p + j < lim ? cols[p + j] : -1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) f[j] = u[j] >= 0 ? F[u[j]] : 0ull;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (need && u[j] >= 0) {
+                const uint64_t x = f[j] & need;
+                if (x) {
+                    record(par_vm, lvl_vm, v, x, u[j], level);
+                    found |= x;
+                    need &= ~x;
+                }
+                ++p;
+            }
         }
-        ++p;
     }
     int64_t ex = p - beg;
     uint64_t rem = __ballot(need != 0 && p < end);
