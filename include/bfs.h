@@ -121,7 +121,14 @@ typedef struct {
                               when the frontier bitmap (n/8 bytes) is larger
                               than the device's L2 cache, else 2; 1 = its first
                               three row entries (MIN always uses these)        */
-    int32_t reserved[4];
+    int32_t td_prepass;    /* ANY parents (fetch-or claims), direction-optimizing:
+                              a top-down level with at least this many frontier
+                              edges first lets every unvisited vertex probe its
+                              two hub neighbours (as bu_head 3) and takes the
+                              hits; the edge pass then finds them visited.
+                              Needs hub ranks.  0 = default (2^24), negative =
+                              never                                            */
+    int32_t reserved[3];
 } bfs_opts;
 
 typedef struct {

@@ -45,7 +45,7 @@ class bfs_opts(ctypes.Structure):
                 ("beta", ctypes.c_double), ("timing", ctypes.c_int32), ("bu_serial", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("td_claim", ctypes.c_int32), ("small_edges", ctypes.c_int32),
                 ("persist_edges", ctypes.c_int32), ("persist_groups", ctypes.c_int32),
-                ("bu_head", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("bu_head", ctypes.c_int32), ("td_prepass", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class bfs_stats(ctypes.Structure):

@@ -9,6 +9,7 @@ direction-invariant; the GPU tests check both):
   small_edges   persistent top-down engine on (0, default caps) or off (-1)
   bu_head       bottom-up probes for ANY parents: automatic (0), row order (1),
                 three highest-degree neighbours (2), two hub-ranked neighbours (3)
+  td_prepass    hub pre-pass of heavy top-down levels: default threshold (0) or off (-1)
 
 The search is a coordinate descent: (alpha, beta) on a grid first, then each
 remaining knob in turn, every candidate timed as the mean wall time of the
@@ -33,6 +34,7 @@ GRIDS = (2048, 1024, 4096)
 CLAIMS = (0, 1)
 ENGINE = (0, -1)
 HEADS = (0, 1, 2, 3)
+PREPASS = (0, -1)
 
 
 def _key(g, k: int) -> str:
@@ -90,7 +92,7 @@ def tune(g, sources, k: int = 1, cache_path: str | None = None, reps: int = 3, v
             bfs_run_multi(g, batch, par, dep, ws, o)
 
     best = {"alpha": 15.0, "beta": 18.0, "bu_serial": 16, "grid_blocks": 2048, "td_claim": 0, "small_edges": 0,
-            "bu_head": 0}
+            "bu_head": 0, "td_prepass": 0}
     trials = []
 
     def measure(cfg):
@@ -114,7 +116,8 @@ def tune(g, sources, k: int = 1, cache_path: str | None = None, reps: int = 3, v
             if t < best_t * margin:
                 best, best_t = cfg, t
     for name, values in (("bu_serial", SERIALS), ("grid_blocks", GRIDS), ("td_claim", CLAIMS if k == 1 else ()),
-                         ("small_edges", ENGINE if k == 1 else ()), ("bu_head", HEADS if k == 1 else ())):
+                         ("small_edges", ENGINE if k == 1 else ()), ("bu_head", HEADS if k == 1 else ()),
+                         ("td_prepass", PREPASS if k == 1 else ())):
         for v in values:
             cfg = dict(best, **{name: v})
             if cfg == best:
@@ -132,7 +135,7 @@ def tune(g, sources, k: int = 1, cache_path: str | None = None, reps: int = 3, v
 
 
 def opts_from(result: dict, **extra):
-    cfg = {k: result[k] for k in ("alpha", "beta", "bu_serial", "grid_blocks", "td_claim", "small_edges", "bu_head")
-           if k in result}
+    cfg = {k: result[k] for k in ("alpha", "beta", "bu_serial", "grid_blocks", "td_claim", "small_edges", "bu_head",
+                                  "td_prepass") if k in result}
     cfg.update(extra)
     return bfs_opts_default(**cfg)

@@ -386,6 +386,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     bool engine_on = o.small_edges >= 0;
     const int64_t cap_one = o.small_edges > 0 ? o.small_edges : 1024;
     const int64_t cap_multi = o.persist_edges > 0 ? std::max<int64_t>(o.persist_edges, cap_one) : 65536;
+    const int64_t prepass_edges = o.td_prepass > 0 ? o.td_prepass : o.td_prepass == 0 ? ((int64_t)1 << 24) : -1;
     int pgroups = o.persist_groups > 0 ? o.persist_groups : 64;
     pgroups = std::min(pgroups, g->persist_groups_max);
     if (pgroups < 1) pgroups = 1;
@@ -393,6 +394,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     int64_t* d_rec = (int64_t*)(ws + Lo.rec);
     int level = 0;
     int64_t reached = 1, examined = 0;
+    bool prev_bu = false;      // the previous level ran bottom-up
     bool same_level = false;   // retrying this level: its direction is already chosen
     bool skip_engine = false;  // ... and it goes through the per-level kernels
     for (;;) {
@@ -485,7 +487,10 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             unvisited -= hs.found;
             level += (int)hs.levels_done;
             if (hs.cur_is_b) { int32_t* t = qcur; qcur = qnext; qnext = t; }
-            if (hs.levels_done > 0) fbits_stale = true;
+            if (hs.levels_done > 0) {
+                fbits_stale = true;
+                prev_bu = false;
+            }
             if (hs.reason == ENG_EMPTY) break;   // the next frontier is empty
             qlen = hs.qlen;
             n_f = hs.n_f;
@@ -505,8 +510,36 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
         uint64_t* zslot = counters + (size_t)((level + 1) % SLOTS) * SLOT_WORDS;
 
         const int32_t next_depth = level + 1;
+        bool prepass = false;
         if (cur_dir == 0) {
             if (m_f > 0) {
+                // a heavy top-down level of an any-parent search first lets
+                // every unvisited vertex check its two hub neighbours in the
+                // on-chip copy of the hubs' frontier bits; those it finds are
+                // visited before the edge pass, whose probes then skip them,
+                // which saves most of its claim atomics
+                prepass = claim_mode == CLAIM_BITMAP && o.dir == BFS_DIR_DO && g->nhub > 0 && prepass_edges >= 0 &&
+                          m_f >= prepass_edges;
+                if (prepass) {
+                    HIP_TRY(T.begin(BFS_K_CONVERT));
+                    if (fbits_stale) {
+                        launch_clear_words(L, fbits, W);
+                        launch_queue_to_bitmap(L, qcur, qlen, fbits);
+                        fbits_stale = false;
+                    }
+                    uint64_t* hb = (uint64_t*)(ws + Lo.hb);
+                    launch_hub_gather(L, fbits, g->d_hubid, g->nhub, hb);
+                    HIP_TRY(hipGetLastError());
+                    HIP_TRY(T.end(BFS_K_CONVERT, level));
+                    HIP_TRY(T.begin(BFS_K_TD_EXPAND));
+                    launch_bu_sweep<OffT>(L, g->d_hubr, 3, g->d_iso, g->d_nbase, off, g->cols, fbits, hb, nbits,
+                                          visited, vprev, parent, depth, W, next_depth, serial, slot, zslot,
+                                          !out_filled, n, src);
+                    out_filled = true;
+                    HIP_TRY(hipGetLastError());
+                    HIP_TRY(T.end(BFS_K_TD_EXPAND, level));
+                    if (st) { st->launches[BFS_K_CONVERT] += 1; st->launches[BFS_K_TD_EXPAND] += 1; }
+                }
                 HIP_TRY(T.begin(BFS_K_TD_SCAN));
                 int nl = launch_td_scan<OffT>(L, off, qcur, qlen_dev, qlen, scan, tiles, partial, nullptr);
                 HIP_TRY(hipGetLastError());
@@ -539,7 +572,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                 if (st) st->launches[BFS_K_CONVERT] += 2;
                 fbits_stale = false;
             }
-            const bool from_td = fmt_queue;   // the previous level ran top-down
+            const bool from_td = !prev_bu;   // the previous level ran top-down
             fmt_queue = false;
             // any-parent searches probe the highest-degree neighbours first.
             // On a bottom-up level entered from top-down (small frontier, many
@@ -592,7 +625,13 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
         m_u -= m_next;
         n_f = n_next;
         m_f = m_next;
-        if (cur_dir == 0) {
+        prev_bu = cur_dir == 1;
+        if (prepass) {
+            // the next frontier is the merge's bitmap (the queue holds only
+            // the edge pass's winners)
+            fmt_queue = false;
+            qlen_dev = nullptr;
+        } else if (cur_dir == 0) {
             qlen = (int64_t)h[S_QLEN];
             qlen_dev = nullptr;
             int32_t* t = qcur; qcur = qnext; qnext = t;

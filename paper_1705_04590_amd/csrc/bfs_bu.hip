@@ -49,6 +49,9 @@ __device__ __forceinline__ uint64_t stream_load(const uint64_t* p) { return __bu
 // high-degree vertices), so fewer probes are made; a miss then scans the whole
 // row from its start.
 //
+// HUB = 3: HUB = 2's probes only, as the pre-pass of a heavy top-down level
+// (no row scans; only visited is updated, see the level's merge).
+//
 // HUB = 2 (any-parent searches on graphs with hub ranks): the head holds the
 // two neighbours of highest degree and, packed in its last word, their ranks
 // among the graph's hubs (0xFFFF: not a hub).  The frontier bits of all hubs
@@ -61,7 +64,7 @@ __device__ __forceinline__ uint64_t stream_load(const uint64_t* p) { return __bu
 // unreached vertices get -1, 64 consecutive entries per store, so together
 // with the hits every line of the outputs is written once on this level.
 template <typename OffT, int HUB, int FILL>
-__global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
+__device__ __forceinline__ void bu_sweep_body(
     const int4* __restrict__ head, const uint64_t* __restrict__ iso, const uint32_t* __restrict__ nbase,
     const OffT* __restrict__ off, const int32_t* __restrict__ cols,
     const uint64_t* __restrict__ fbits, const uint64_t* __restrict__ hb, uint64_t* __restrict__ nbits,
@@ -72,8 +75,8 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
     __shared__ int32_t s_list[BU_BLOCK / WAVE][BU_WIN];
     __shared__ int32_t s_hidx[BU_BLOCK / WAVE][BU_WIN];
     __shared__ unsigned long long s_nb[BU_BLOCK / WAVE][WAVE];
-    __shared__ uint64_t s_hb[HUB == 2 ? HUB_BITS / 64 : 1];
-    if (HUB == 2) {
+    __shared__ uint64_t s_hb[HUB >= 2 ? HUB_BITS / 64 : 1];
+    if (HUB >= 2) {
         for (int i = threadIdx.x; i < HUB_BITS / 64; i += BU_BLOCK) s_hb[i] = hb[i];
         __syncthreads();
     }
@@ -140,8 +143,8 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
                 int32_t par = -1;
                 int32_t pos = 0;   // position of the hit in the row
                 // entries the head probes; with HUB = 2 its last word holds ranks
-                constexpr int32_t nprobe = HUB == 2 ? 2 : 3;
-                if (HUB == 2) {
+                constexpr int32_t nprobe = HUB >= 2 ? 2 : 3;
+                if (HUB >= 2) {
                     const uint32_t r0 = (uint32_t)h.w & 0xFFFFu, r1 = (uint32_t)h.w >> 16;
                     // both probes are issued before either is tested
                     const uint64_t f0 = deg > 0 ? (r0 != 0xFFFFu ? s_hb[r0 >> 6] : fbits[h.y >> 6]) : 0ull;
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
                 constexpr int32_t skip = HUB ? 0 : 3, pbase = HUB ? nprobe : 0;
                 int64_t beg = 0;
                 int32_t rp = deg;   // next entry to scan; deg when nothing is left
-                if (par < 0 && deg > nprobe) {
+                if (HUB != 3 && par < 0 && deg > nprobe) {
                     beg = (int64_t)off[v];
                     const int32_t lim = deg - skip > serial_len ? skip + serial_len : deg;
                     const int32_t* row = cols + beg;
@@ -180,7 +183,7 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
                     if (par >= 0) pos = pbase + rp;
                     else if (rp > lim) rp = lim;
                 }
-                uint64_t rem = __ballot(par < 0 && rp < deg);
+                uint64_t rem = HUB == 3 ? 0ull : __ballot(par < 0 && rp < deg);
                 while (rem) {
                     const int l = __ffsll((unsigned long long)rem) - 1;
                     rem &= rem - 1;
@@ -216,10 +219,16 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
         }
         const uint64_t nb = nbw[lane];
         if (mine) {
-            nbits[w] = nb;
-            if (nb) {
-                visited[w] = wv | nb;
-                vprev[w] = wv | nb;
+            if (HUB == 3) {
+                // pre-pass of a top-down level: only visited changes; the
+                // level's merge finds these vertices as new (visited & ~vprev)
+                if (nb) visited[w] = wv | nb;
+            } else {
+                nbits[w] = nb;
+                if (nb) {
+                    visited[w] = wv | nb;
+                    vprev[w] = wv | nb;
+                }
             }
         }
         if (FILL) {
@@ -246,6 +255,32 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(
     block_add3<BU_BLOCK / WAVE>(my_n, my_m, my_x, &ln[S_NNEXT], &ln[S_MNEXT], &ln[S_EXAMINED]);
 }
 
+#define BFS_SWEEP_PARAMS                                                                                          \
+    const int4* __restrict__ head, const uint64_t* __restrict__ iso, const uint32_t* __restrict__ nbase,          \
+        const OffT* __restrict__ off, const int32_t* __restrict__ cols, const uint64_t* __restrict__ fbits,        \
+        const uint64_t* __restrict__ hb, uint64_t* __restrict__ nbits, uint64_t* __restrict__ visited,             \
+        uint64_t* __restrict__ vprev, int32_t* __restrict__ parent, int32_t* __restrict__ depth, int64_t W, int GW, \
+        int32_t next_depth, int serial_len, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot, int64_t n,  \
+        int64_t src
+#define BFS_SWEEP_ARGS                                                                                            \
+    head, iso, nbase, off, cols, fbits, hb, nbits, visited, vprev, parent, depth, W, GW, next_depth, serial_len,   \
+        slot, zslot, n, src
+
+// the bottom-up step
+template <typename OffT, int HUB, int FILL>
+__global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(BFS_SWEEP_PARAMS) {
+    bu_sweep_body<OffT, HUB, FILL>(BFS_SWEEP_ARGS);
+}
+
+// the hub pre-pass of a heavy top-down level (a kernel of its own name, so
+// profiles keep it apart from the bottom-up step)
+template <typename OffT, int FILL>
+__global__ __launch_bounds__(BU_BLOCK) void k_td_hub_prepass(BFS_SWEEP_PARAMS) {
+    bu_sweep_body<OffT, 3, FILL>(BFS_SWEEP_ARGS);
+}
+#undef BFS_SWEEP_PARAMS
+#undef BFS_SWEEP_ARGS
+
 // words per group: 64 when that still gives every wave of the grid several
 // groups, fewer on small graphs so the sweep spreads over the whole chip
 static int group_words(int64_t W, int waves) {
@@ -267,16 +302,23 @@ void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t*
     hipLaunchKernelGGL((k_bu_sweep<OffT, H, F>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off, cols, \
                        fbits, hb, nbits, visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot, zslot, n, \
                        src)
+#define BFS_PREPASS(F)                                                                                              \
+    hipLaunchKernelGGL((k_td_hub_prepass<OffT, F>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off,    \
+                       cols, fbits, hb, nbits, visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot,     \
+                       zslot, n, src)
     if (fill) {
-        if (hub == 2) BFS_SWEEP(2, 1);
+        if (hub == 3) BFS_PREPASS(1);
+        else if (hub == 2) BFS_SWEEP(2, 1);
         else if (hub == 1) BFS_SWEEP(1, 1);
         else BFS_SWEEP(0, 1);
     } else {
-        if (hub == 2) BFS_SWEEP(2, 0);
+        if (hub == 3) BFS_PREPASS(0);
+        else if (hub == 2) BFS_SWEEP(2, 0);
         else if (hub == 1) BFS_SWEEP(1, 0);
         else BFS_SWEEP(0, 0);
     }
 #undef BFS_SWEEP
+#undef BFS_PREPASS
 }
 
 // ------------------------------------------------------------------ row heads

@@ -83,7 +83,8 @@ void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t*
                       int32_t next_depth);
 
 // head kinds (hub): 0 row heads, 1 hub heads, 2 hub heads with hub ranks
-// (then hb holds the hubs' frontier bits, HUB_BITS bits).  fill: the outputs
+// (then hb holds the hubs' frontier bits, HUB_BITS bits), 3 the same probes
+// only, as a pre-pass of a top-down level (visited updated, nbits/vprev not).  fill: the outputs
 // were not initialised; the sweep also writes -1 to every entry of the
 // unreached and isolated vertices (the source, of id src, excepted)
 template <typename OffT>

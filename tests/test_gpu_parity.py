@@ -121,11 +121,15 @@ def test_parity_all_modes(orc, graphs, name, direction):
         dg = get(graphs, name, off_dtype)
         for s in sources_for(dg.off):
             ref = orc.bfs_min(dg.off, dg.cols, int(s))
-            for pm, claim, head in ((bfs.BFS_PARENT_ANY, 0, 0), (bfs.BFS_PARENT_ANY, 1, 0),
-                                    (bfs.BFS_PARENT_ANY, 0, 1), (bfs.BFS_PARENT_ANY, 0, 2),
-                                    (bfs.BFS_PARENT_ANY, 0, 3), (bfs.BFS_PARENT_MIN, 0, 0),
-                                    (bfs.BFS_PARENT_MIN, 0, 3)):
-                p, d, st = dg.run(s, dir=dirv, parent_mode=pm, td_claim=claim, bu_head=head)
+            for pm, claim, head, pre in ((bfs.BFS_PARENT_ANY, 0, 0, 0), (bfs.BFS_PARENT_ANY, 1, 0, 0),
+                                         (bfs.BFS_PARENT_ANY, 0, 1, 0), (bfs.BFS_PARENT_ANY, 0, 2, 0),
+                                         (bfs.BFS_PARENT_ANY, 0, 3, 0), (bfs.BFS_PARENT_MIN, 0, 0, 0),
+                                         (bfs.BFS_PARENT_MIN, 0, 3, 0), (bfs.BFS_PARENT_ANY, 0, 0, 1),
+                                         (bfs.BFS_PARENT_ANY, 0, 2, 1), (bfs.BFS_PARENT_MIN, 0, 0, 1)):
+                # pre = 1: every top-down level with an edge runs the hub
+                # pre-pass (engine off, so the small levels do too)
+                p, d, st = dg.run(s, dir=dirv, parent_mode=pm, td_claim=claim, bu_head=head, td_prepass=pre,
+                                  small_edges=-1 if pre else 0)
                 check(orc, dg, s, p, d, pm == bfs.BFS_PARENT_MIN, ref)
                 assert st.reached == int((d >= 0).sum())
                 assert st.isolated == int((np.diff(dg.off) == 0).sum())
@@ -170,6 +174,8 @@ def test_config1_scale16_int32_offsets(orc, graphs):
         for head in (2, 3):
             p, d, _ = dg.run(s, parent_mode=bfs.BFS_PARENT_ANY, bu_head=head)
             check(orc, dg, s, p, d, False, ref)
+        p, d, _ = dg.run(s, parent_mode=bfs.BFS_PARENT_ANY, td_prepass=1, small_edges=-1)
+        check(orc, dg, s, p, d, False, ref)
 
 
 def test_tuning_knobs_do_not_change_results(orc, graphs):
@@ -194,7 +200,8 @@ def test_outputs_fully_written(orc, graphs, name):
             ref = orc.bfs_min(dg.off, dg.cols, int(s))
             for kw in (dict(), dict(dir=bfs.BFS_DIR_BU), dict(dir=bfs.BFS_DIR_TD), dict(alpha=1e-9),
                        dict(alpha=1e9, beta=1e9), dict(small_edges=-1), dict(td_claim=1),
-                       dict(parent_mode=bfs.BFS_PARENT_MIN)):
+                       dict(parent_mode=bfs.BFS_PARENT_MIN), dict(td_prepass=1, small_edges=-1),
+                       dict(td_prepass=1, small_edges=-1, alpha=1e9, beta=1e9)):
                 p, d, _ = dg.run(s, **kw)
                 check(orc, dg, s, p, d, kw.get("parent_mode") == bfs.BFS_PARENT_MIN, ref)
                 assert (p >= -1).all() and (d >= -1).all()
