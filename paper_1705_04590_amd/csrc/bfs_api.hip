@@ -283,8 +283,11 @@ struct Timer {
 
     hipError_t ensure(size_t k) {
         while (g->events.size() < k) {
+            // timing only (read after a stream synchronisation): no system-scope
+            // fence, whose cache writeback and invalidation would slow the
+            // kernel that follows the event
             hipEvent_t e;
-            hipError_t r = hipEventCreate(&e);
+            hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
             if (r != hipSuccess) return r;
             g->events.push_back(e);
         }
