@@ -460,17 +460,39 @@ __global__ __launch_bounds__(256) void k_ms_output(int64_t n, int k, const int64
             s_vis[threadIdx.x] = vis;
         }
         __syncthreads();
-        // read: 64 vertices x 64 entries, consecutive threads on consecutive sources
-        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-            const int vi = e >> 6, j = e & 63;
+        // read: four threads per vertex, 16 sources each, with 16-byte loads
+        // of its rows (only for vertices some source reached)
+        {
+            const int vi = threadIdx.x >> 2, j0 = (threadIdx.x & 3) * 16;
             const int64_t v = v0 + vi;
-            int32_t pv = -1, dv = -1;
-            if (v < n && j < k && ((s_vis[vi] >> j) & 1ull)) {
-                pv = par_vm[v * 64 + j];
-                dv = lvl_vm[v * 64 + j];
+            const uint32_t bits = (uint32_t)(s_vis[vi] >> j0) & 0xFFFFu;
+            int32_t pv[16];
+            uint16_t dv[16];
+            if (v < n && bits) {
+                const int4* pp = (const int4*)(par_vm + v * 64 + j0);
+                const uint4* lp = (const uint4*)(lvl_vm + v * 64 + j0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int4 x = pp[q];
+                    pv[4 * q] = x.x; pv[4 * q + 1] = x.y; pv[4 * q + 2] = x.z; pv[4 * q + 3] = x.w;
+                }
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const uint4 x = lp[q];
+                    const uint32_t w4[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        dv[8 * q + 2 * r] = (uint16_t)(w4[r] & 0xFFFFu);
+                        dv[8 * q + 2 * r + 1] = (uint16_t)(w4[r] >> 16);
+                    }
+                }
             }
-            s_p[vi][j] = pv;
-            s_d[vi][j] = dv;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const bool on = (bits >> j) & 1u;
+                s_p[vi][j0 + j] = on ? pv[j] : -1;
+                s_d[vi][j0 + j] = on ? (int32_t)dv[j] : -1;
+            }
         }
         __syncthreads();
         // write: for each source, 64 consecutive vertices
