@@ -207,6 +207,19 @@ def test_outputs_fully_written(orc, graphs, name):
                 assert (p >= -1).all() and (d >= -1).all()
 
 
+def test_uniform_degree_graph_has_no_hubs(orc):
+    """A 300 x 300 grid: over 65 535 vertices share the top degree, so no hub
+    threshold exists and the hub-ranked modes fall back to the plain heads."""
+    off, cols = graphgen.grid2d(300, 300)
+    dg = DevGraph(off, cols, np.int32)
+    for s in (0, 45150, 89999):
+        ref = orc.bfs_min(off, cols, s)
+        for kw in (dict(bu_head=3), dict(bu_head=0), dict(td_prepass=1, small_edges=-1),
+                   dict(parent_mode=bfs.BFS_PARENT_MIN)):
+            p, d, _ = dg.run(s, **kw)
+            check(orc, dg, s, p, d, kw.get("parent_mode") == bfs.BFS_PARENT_MIN, ref)
+
+
 def test_repeat_runs_identical(graphs):
     dg = get(graphs, "kron14")
     s = int(graphgen.random_sources(dg.off, 1, seed=9)[0])
