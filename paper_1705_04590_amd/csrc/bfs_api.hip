@@ -157,7 +157,7 @@ bfs_status readback(HostCtx* c, hipStream_t s, const void* src, int nw, const ui
 // -------------------------------------------------------------- workspace layout
 struct SingleLayout {
     size_t counters, pctl, pctr, small, ctl_end, rec, visited, vprev, fbits, nbits, claim, q0, q1, scan, tiles, partial,
-        hb, total;
+        hb, pcsum, total;
 };
 
 SingleLayout single_layout(const bfs_graph* g) {
@@ -186,6 +186,8 @@ SingleLayout single_layout(const bfs_graph* g) {
     L.tiles = o; o = align_up(o + sizeof(int32_t) * (size_t)(ntiles + 2));
     L.partial = o; o = align_up(o + sizeof(int64_t) * (size_t)((n + SCAN_TILE - 1) / SCAN_TILE + 2));
     L.hb = o; o = align_up(o + sizeof(uint64_t) * (HUB_BITS / 64));
+    // per-workgroup edge totals of the engine's edge-balanced levels
+    L.pcsum = o; o = align_up(o + sizeof(int64_t) * (size_t)(g->persist_groups_max > 0 ? g->persist_groups_max : 1));
     L.total = o;
     return L;
 }
@@ -440,7 +442,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             launch_td_persist<OffT>(L, claim_mode, groups, off, g->cols, parent, depth, visited, vprev, claim, qcur,
                                     qnext, n, in, d_small, (uint64_t*)(ws + Lo.pctr), (PersistCtl*)(ws + Lo.pctl),
                                     d_rec, rec_cap, eng_alpha, multi ? cap_multi : cap_one, multi ? cap_one / 2 : 0,
-                                    (int64_t)1 << 40);
+                                    (int64_t)1 << 40, scan, tiles, (int64_t*)(ws + Lo.pcsum));
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_TD_EXPAND, -1));
             // state and level records in one copy, then the whole control

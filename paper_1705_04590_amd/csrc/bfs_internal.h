@@ -151,7 +151,8 @@ template <typename OffT>
 void launch_td_persist(const Launch& L, int mode, int groups, const OffT* off, const int32_t* cols, int32_t* parent,
                        int32_t* depth, uint64_t* visited, uint64_t* vprev, uint64_t* claim, int32_t* qa, int32_t* qb,
                        int64_t n, SmallIn in, SmallState* st, uint64_t* ctr, PersistCtl* ctl, int64_t* rec,
-                       int rec_cap, double alpha, int64_t edge_cap, int64_t shrink_below, int64_t max_levels);
+                       int rec_cap, double alpha, int64_t edge_cap, int64_t shrink_below, int64_t max_levels,
+                       int64_t* gscan, int32_t* gtiles, int64_t* csum);
 // queue = set bits of `bits` in ascending order, *qlen_ctr = their count;
 // partial: scan scratch of ceil(W / SCAN_TILE) + 2 int64.  Returns launches.
 int launch_bitmap_to_queue(const Launch& L, const uint64_t* bits, int64_t W, int32_t* q, uint64_t* qlen_ctr,

@@ -45,6 +45,8 @@ namespace bfsk {
 
 constexpr int PT_BLOCK = 256;
 constexpr int PT_WIN = 1024;             // LDS winner buffer per workgroup
+constexpr int PT_TILE = TD_TILE;         // edges per tile of an edge-balanced level
+constexpr int PT_BAL_AVG = 16;           // average frontier degree from which levels are edge-balanced
 constexpr uint32_t ROLL_POISON = 1u << 30;
 
 template <typename T>
@@ -114,7 +116,12 @@ __global__ __launch_bounds__(PT_BLOCK) void k_td_persist(
     uint64_t* __restrict__ claim, int32_t* __restrict__ qa, int32_t* __restrict__ qb, int64_t n, SmallIn in,
     SmallState* __restrict__ st, uint64_t* __restrict__ ctr, PersistCtl* __restrict__ ctl, int64_t* __restrict__ rec,
     int rec_cap, double alpha, int64_t edge_cap, int64_t shrink_below, int64_t max_levels, long long roll_ticks,
-    long long bar_ticks) {
+    long long bar_ticks, int64_t* __restrict__ gscan, int32_t* __restrict__ gtiles, int64_t* __restrict__ csum) {
+    // edge-balanced levels: a tile of PT_TILE edges staged per step
+    __shared__ int32_t s_tu[PT_TILE + 1];
+    __shared__ int32_t s_ts[PT_TILE + 1];
+    __shared__ int64_t s_tb[PT_TILE + 1];
+    __shared__ int64_t s_E;
     __shared__ int32_t s_u[PT_BLOCK];
     __shared__ int64_t s_row[PT_BLOCK];
     __shared__ int64_t s_pre[PT_BLOCK + 1];
@@ -168,81 +175,177 @@ __global__ __launch_bounds__(PT_BLOCK) void k_td_persist(
         const int64_t i_beg = min(qlen, (int64_t)g * C), i_end = min(qlen, i_beg + C);
         if (MODE != CLAIM_MIN && done > 0) fold_vprev(0, nz_cur);   // back part of the previous winners
         __syncthreads();
-        for (int64_t c0 = i_beg; c0 < i_end; c0 += PT_BLOCK) {
-            const int64_t i = c0 + tid;
-            int64_t d = 0;
-            if (i < i_end) {
-                const int32_t u = ld_dev(&qcur[i]);
-                if (MODE != CLAIM_MIN && done > 0) atomicOr((unsigned long long*)&vprev[u >> 6], 1ull << (u & 63));
-                const int64_t b = (int64_t)off[u];
-                d = (int64_t)off[u + 1] - b;
-                s_u[tid] = u;
-                s_row[tid] = b;
-            }
-            const int64_t inc = wave_incl_scan(d);
-            if (lane == WAVE - 1) s_wsum[tid / WAVE] = inc;
-            __syncthreads();
-            int64_t before = 0;
-            for (int k = 0; k < tid / WAVE; ++k) before += s_wsum[k];
-            const int64_t ex = before + inc - d;
-            s_pre[tid] = ex;
-            if (tid == PT_BLOCK - 1) s_pre[PT_BLOCK] = ex + d;
-            __syncthreads();
-            const int nv = (int)min((int64_t)PT_BLOCK, i_end - c0);
-            const int64_t E = s_pre[nv];
-            for (int64_t e0 = 0; e0 < E; e0 += PT_BLOCK) {
-                const int64_t e = e0 + tid;
-                int32_t v = 0;
-                bool won = false;
-                if (e < E) {
-                    int lo = 0, hi = nv - 1;   // last vertex whose edges start at or before e
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (s_pre[mid] <= e) lo = mid; else hi = mid - 1;
-                    }
-                    const int32_t u = s_u[lo];
-                    v = cols[s_row[lo] + (e - s_pre[lo])];
-                    const uint64_t bit = 1ull << (v & 63);
-                    const uint64_t vw = ld_dev(&visited[v >> 6]);
-                    if (!(vw & bit)) {
-                        if (MODE == CLAIM_MIN) {
-                            atomicMin((unsigned int*)&parent[v], (unsigned int)u);
-                            won = !(atomicOr((unsigned long long*)&claim[v >> 6], (unsigned long long)bit) & bit);
-                        } else if (MODE == CLAIM_CAS) {
-                            won = atomicCAS(&parent[v], -1, u) == -1;
-                            if (won) atomicOr((unsigned long long*)&visited[v >> 6], (unsigned long long)bit);
-                        } else {
-                            won = !(atomicOr((unsigned long long*)&visited[v >> 6], (unsigned long long)bit) & bit);
-                            if (won) parent[v] = u;
-                        }
+        // one edge per thread: the claim, the winner's outputs and its place
+        // in the LDS winner buffers, flushed to the next queue when another
+        // step could overflow them (all threads call this together)
+        auto edge_step = [&](bool valid, int32_t u, int32_t v) {
+            bool won = false;
+            if (valid) {
+                const uint64_t bit = 1ull << (v & 63);
+                const uint64_t vw = ld_dev(&visited[v >> 6]);
+                if (!(vw & bit)) {
+                    if (MODE == CLAIM_MIN) {
+                        atomicMin((unsigned int*)&parent[v], (unsigned int)u);
+                        won = !(atomicOr((unsigned long long*)&claim[v >> 6], (unsigned long long)bit) & bit);
+                    } else if (MODE == CLAIM_CAS) {
+                        won = atomicCAS(&parent[v], -1, u) == -1;
+                        if (won) atomicOr((unsigned long long*)&visited[v >> 6], (unsigned long long)bit);
+                    } else {
+                        won = !(atomicOr((unsigned long long*)&visited[v >> 6], (unsigned long long)bit) & bit);
+                        if (won) parent[v] = u;
                     }
                 }
-                int64_t dv = 0;
-                if (won) {
-                    depth[v] = next_depth;
-                    dv = (int64_t)off[v + 1] - (int64_t)off[v];
-                    my_n += 1;
-                    my_m += (uint64_t)dv;
-                    if (dv > 0) s_win[atomicAdd(&s_nw, 1)] = v;
-                    else s_win0[atomicAdd(&s_nw0, 1)] = v;
+            }
+            if (won) {
+                depth[v] = next_depth;
+                const int64_t dv = (int64_t)off[v + 1] - (int64_t)off[v];
+                my_n += 1;
+                my_m += (uint64_t)dv;
+                if (dv > 0) s_win[atomicAdd(&s_nw, 1)] = v;
+                else s_win0[atomicAdd(&s_nw0, 1)] = v;
+            }
+            __syncthreads();
+            const int nw = s_nw, nw0 = s_nw0;
+            if (nw > PT_WIN - PT_BLOCK || nw0 > PT_WIN - PT_BLOCK) {
+                if (tid == 0) {
+                    s_base = nw ? atomicAdd((unsigned long long*)&slot[0], (unsigned long long)nw) : 0;
+                    s_base0 = nw0 ? atomicAdd((unsigned long long*)&slot[4], (unsigned long long)nw0) : 0;
                 }
                 __syncthreads();
-                // flush when another round could overflow a buffer
-                const int nw = s_nw, nw0 = s_nw0;
-                if (nw > PT_WIN - PT_BLOCK || nw0 > PT_WIN - PT_BLOCK) {
-                    if (tid == 0) {
-                        s_base = nw ? atomicAdd((unsigned long long*)&slot[0], (unsigned long long)nw) : 0;
-                        s_base0 = nw0 ? atomicAdd((unsigned long long*)&slot[4], (unsigned long long)nw0) : 0;
-                    }
-                    __syncthreads();
-                    for (int j = tid; j < nw; j += PT_BLOCK) qnext[s_base + j] = s_win[j];
-                    for (int j = tid; j < nw0; j += PT_BLOCK) qnext[n - 1 - (int64_t)(s_base0 + j)] = s_win0[j];
-                    __syncthreads();
-                    if (tid == 0) { s_nw = 0; s_nw0 = 0; }
-                    __syncthreads();
+                for (int j = tid; j < nw; j += PT_BLOCK) qnext[s_base + j] = s_win[j];
+                for (int j = tid; j < nw0; j += PT_BLOCK) qnext[n - 1 - (int64_t)(s_base0 + j)] = s_win0[j];
+                __syncthreads();
+                if (tid == 0) { s_nw = 0; s_nw0 = 0; }
+                __syncthreads();
+            }
+        };
+        // a frontier of high average degree (hub rows) is split by edges over
+        // all workgroups: a grid-wide degree prefix sum and a tile table
+        // first, two barriers; otherwise each workgroup expands the rows of
+        // its own queue chunk
+        const bool bal = G > 1 && m_f >= (int64_t)PT_BAL_AVG * qlen;
+        if (!bal) {
+            for (int64_t c0 = i_beg; c0 < i_end; c0 += PT_BLOCK) {
+                const int64_t i = c0 + tid;
+                int64_t d = 0;
+                if (i < i_end) {
+                    const int32_t u = ld_dev(&qcur[i]);
+                    if (MODE != CLAIM_MIN && done > 0) atomicOr((unsigned long long*)&vprev[u >> 6], 1ull << (u & 63));
+                    const int64_t b = (int64_t)off[u];
+                    d = (int64_t)off[u + 1] - b;
+                    s_u[tid] = u;
+                    s_row[tid] = b;
                 }
+                const int64_t inc = wave_incl_scan(d);
+                if (lane == WAVE - 1) s_wsum[tid / WAVE] = inc;
+                __syncthreads();
+                int64_t before = 0;
+                for (int k = 0; k < tid / WAVE; ++k) before += s_wsum[k];
+                const int64_t ex = before + inc - d;
+                s_pre[tid] = ex;
+                if (tid == PT_BLOCK - 1) s_pre[PT_BLOCK] = ex + d;
+                __syncthreads();
+                const int nv = (int)min((int64_t)PT_BLOCK, i_end - c0);
+                const int64_t E = s_pre[nv];
+                for (int64_t e0 = 0; e0 < E; e0 += PT_BLOCK) {
+                    const int64_t e = e0 + tid;
+                    int32_t u = 0, v = 0;
+                    if (e < E) {
+                        int lo = 0, hi = nv - 1;   // last vertex whose edges start at or before e
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (s_pre[mid] <= e) lo = mid; else hi = mid - 1;
+                        }
+                        u = s_u[lo];
+                        v = cols[s_row[lo] + (e - s_pre[lo])];
+                    }
+                    edge_step(e < E, u, v);
+                }
+                __syncthreads();
+            }
+        } else {
+            // (1) the chunk's degrees: local exclusive prefix into gscan, total into csum[g]
+            int64_t carry = 0;
+            for (int64_t c0 = i_beg; c0 < i_end; c0 += PT_BLOCK) {
+                const int64_t i = c0 + tid;
+                int64_t d = 0;
+                if (i < i_end) {
+                    const int32_t u = ld_dev(&qcur[i]);
+                    if (MODE != CLAIM_MIN && done > 0) atomicOr((unsigned long long*)&vprev[u >> 6], 1ull << (u & 63));
+                    d = (int64_t)off[u + 1] - (int64_t)off[u];
+                }
+                const int64_t inc = wave_incl_scan(d);
+                if (lane == WAVE - 1) s_wsum[tid / WAVE] = inc;
+                __syncthreads();
+                int64_t before = 0, tot = 0;
+                for (int k = 0; k < PT_BLOCK / WAVE; ++k) {
+                    if (k < tid / WAVE) before += s_wsum[k];
+                    tot += s_wsum[k];
+                }
+                if (i < i_end) gscan[i] = carry + before + inc - d;
+                carry += tot;
+                __syncthreads();
+            }
+            if (tid == 0) csum[g] = carry;
+            if (!grid_sync(ctl, G, nbar++, bar_ticks)) { fail = true; break; }
+            // (2) global offsets; tile t starts in the row of the vertex owning edge t*PT_TILE
+            if (tid == 0) {
+                int64_t coff = 0, E = 0;
+                for (uint32_t h = 0; h < G; ++h) {
+                    const int64_t x = ld_dev(&csum[h]);
+                    if (h < g) coff += x;
+                    E += x;
+                }
+                s_base = (uint64_t)coff;
+                s_E = E;
             }
             __syncthreads();
+            const int64_t coff = (int64_t)s_base, E = s_E;
+            for (int64_t i = i_beg + tid; i < i_end; i += PT_BLOCK) {
+                const int32_t u = ld_dev(&qcur[i]);
+                const int64_t d = (int64_t)off[u + 1] - (int64_t)off[u];
+                const int64_t b = coff + gscan[i];   // written by this same thread in (1)
+                gscan[i] = b;
+                for (int64_t t = (b + PT_TILE - 1) / PT_TILE; t * PT_TILE < b + d; ++t) gtiles[t] = (int32_t)i;
+            }
+            if (!grid_sync(ctl, G, nbar++, bar_ticks)) { fail = true; break; }
+            // (3) the tiles, round robin over the workgroups
+            const int64_t ntiles = (E + PT_TILE - 1) / PT_TILE;
+            for (int64_t t = g; t < ntiles; t += G) {
+                const int64_t e_t0 = t * PT_TILE, e_t1 = min(E, e_t0 + PT_TILE);
+                const int64_t i0 = ld_dev(&gtiles[t]);
+                const int64_t last = t + 1 < ntiles ? (int64_t)ld_dev(&gtiles[t + 1]) : qlen - 1;
+                // every queued vertex has an edge, so a tile spans at most
+                // PT_TILE + 1 of them; the clamps only guard memory
+                int nv = (int)min((int64_t)PT_TILE + 1, last - i0 + 1);
+                if (i0 < 0 || i0 >= qlen) nv = 0;
+                else if (nv > qlen - i0) nv = (int)(qlen - i0);
+                for (int j = tid; j < nv; j += PT_BLOCK) {
+                    const int32_t u = ld_dev(&qcur[i0 + j]);
+                    const int64_t gs = ld_dev(&gscan[i0 + j]);
+                    s_tu[j] = u;
+                    s_ts[j] = (int32_t)(gs > e_t0 ? gs - e_t0 : 0);
+                    s_tb[j] = (int64_t)off[u] - gs;
+                }
+                __syncthreads();
+                for (int64_t e0 = e_t0; e0 < e_t1; e0 += PT_BLOCK) {
+                    const int64_t e = e0 + tid;
+                    const bool valid = e < e_t1 && nv > 0;
+                    int32_t u = 0, v = 0;
+                    if (valid) {
+                        const int p = (int)(e - e_t0);
+                        int lo = 0, hi = nv - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (s_ts[mid] <= p) lo = mid; else hi = mid - 1;
+                        }
+                        u = s_tu[lo];
+                        v = cols[s_tb[lo] + e];
+                    }
+                    edge_step(valid, u, v);
+                }
+                __syncthreads();
+            }
         }
         {
             const int nw = s_nw, nw0 = s_nw0;
@@ -334,13 +437,14 @@ template <typename OffT>
 void launch_td_persist(const Launch& L, int mode, int groups, const OffT* off, const int32_t* cols, int32_t* parent,
                        int32_t* depth, uint64_t* visited, uint64_t* vprev, uint64_t* claim, int32_t* qa, int32_t* qb,
                        int64_t n, SmallIn in, SmallState* st, uint64_t* ctr, PersistCtl* ctl, int64_t* rec,
-                       int rec_cap, double alpha, int64_t edge_cap, int64_t shrink_below, int64_t max_levels) {
+                       int rec_cap, double alpha, int64_t edge_cap, int64_t shrink_below, int64_t max_levels,
+                       int64_t* gscan, int32_t* gtiles, int64_t* csum) {
     // 100 MHz device clock: 2 ms to assemble, 2 s per barrier at most
     const long long roll_ticks = 200000, bar_ticks = 200000000;
 #define BFS_PT(M)                                                                                               \
     hipLaunchKernelGGL((k_td_persist<OffT, M>), dim3(groups), dim3(PT_BLOCK), 0, L.stream, off, cols, parent,   \
                        depth, visited, vprev, claim, qa, qb, n, in, st, ctr, ctl, rec, rec_cap, alpha, edge_cap, \
-                       shrink_below, max_levels, roll_ticks, bar_ticks)
+                       shrink_below, max_levels, roll_ticks, bar_ticks, gscan, gtiles, csum)
     if (mode == CLAIM_MIN) BFS_PT(CLAIM_MIN);
     else if (mode == CLAIM_CAS) BFS_PT(CLAIM_CAS);
     else BFS_PT(CLAIM_BITMAP);
@@ -366,7 +470,7 @@ void launch_queue_to_bitmap(const Launch& L, const int32_t* q, int64_t qlen, uin
     template void launch_td_persist<T>(const Launch&, int, int, const T*, const int32_t*, int32_t*, int32_t*,   \
                                        uint64_t*, uint64_t*, uint64_t*, int32_t*, int32_t*, int64_t, SmallIn,     \
                                        SmallState*, uint64_t*, PersistCtl*, int64_t*, int, double, int64_t,      \
-                                       int64_t, int64_t);
+                                       int64_t, int64_t, int64_t*, int32_t*, int64_t*);
 BFS_PT_INST(int32_t)
 BFS_PT_INST(int64_t)
 
