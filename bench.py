@@ -339,11 +339,21 @@ def configs_bench(args):
         g, keep = resident(off, cols, scale < 22)
         srcs = graphgen.random_sources(off, nsrc, seed=2)
         for name, dv in (("top_down", bfs.BFS_DIR_TD), ("direction_optimizing", bfs.BFS_DIR_DO)):
-            t = singles(g, n, srcs, dir=dv)
+            kw, tuning = dict(dir=dv), "defaults"
+            if dv == bfs.BFS_DIR_DO and not args.no_autotune:
+                # the knobs tuned on sources of another seed, as for the headline run
+                from paper_1705_04590_amd import autotune
+                tuned = autotune.tune(g, graphgen.random_sources(off, 16, seed=99), k=1,
+                                      cache_path=args.tune_cache, force=args.retune)
+                kw = {k: tuned[k] for k in ("alpha", "beta", "bu_serial", "grid_blocks", "td_claim", "small_edges",
+                                            "bu_head", "td_prepass") if k in tuned}
+                kw["dir"] = dv
+                tuning = "autotuned on 16 sources of seed 99" + (" (cached entry)" if tuned.get("cached") else "")
+            t = singles(g, n, srcs, **kw)
             rows.append({"workload": f"kronecker_s{scale}", "mode": name, "sources": nsrc,
                          "offsets": "int32" if scale < 22 else "int64", "ms_per_search": round(t * 1e3, 4),
-                         "gteps": round(m / t / 1e9, 2)})
-            log(f"[configs] kronecker s{scale} {name}: {t * 1e3:.3f} ms/search, {m / t / 1e9:.1f} GTEPS")
+                         "gteps": round(m / t / 1e9, 2), "tuning": tuning})
+            log(f"[configs] kronecker s{scale} {name}: {t * 1e3:.3f} ms/search, {m / t / 1e9:.1f} GTEPS ({tuning})")
         bfs.bfs_destroy_graph(g)
         del keep
     for name, gen, nsingle, reps in (("kronecker_s24", lambda: graphgen.kronecker(24, 16, seed=1), 64, 3),
