@@ -154,11 +154,39 @@ template void launch_post_row<int32_t>(hipStream_t, const int32_t*, int64_t, uin
 template void launch_post_row<int64_t>(hipStream_t, const int64_t*, int64_t, uint64_t*, uint64_t);
 
 // ------------------------------------------------------------------ frontier degree scan
+// the first pass of a multi-block scan keeps the gathered degrees in `scan`,
+// so the second pass reads them in order instead of gathering the offsets
+// again (each item is read and then overwritten by the same thread)
+template <typename OffT>
+struct QueueDegreeKeep {
+    const OffT* off;
+    const int32_t* q;
+    int64_t* keep;
+    __device__ int64_t operator()(int64_t i) const {
+        const int32_t u = q[i];
+        const int64_t d = (int64_t)off[u + 1] - (int64_t)off[u];
+        keep[i] = d;
+        return d;
+    }
+};
+struct KeptValue {
+    const int64_t* keep;
+    __device__ int64_t operator()(int64_t i) const { return keep[i]; }
+};
+
 template <typename OffT>
 int launch_td_scan(const Launch& L, const OffT* off, const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host,
                    int64_t* scan, int32_t* tile_start, int64_t* partial, int64_t* total_out) {
-    return launch_scan(L.stream, QueueDegree<OffT>{off, q}, qlen_dev, qlen_host, partial,
-                       TileSink{scan, tile_start, total_out});
+    const int64_t nb = (qlen_host + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb <= 1)
+        return launch_scan(L.stream, QueueDegree<OffT>{off, q}, qlen_dev, qlen_host, partial,
+                           TileSink{scan, tile_start, total_out});
+    hipLaunchKernelGGL((k_scan_partials_g<QueueDegreeKeep<OffT>>), dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, L.stream,
+                       QueueDegreeKeep<OffT>{off, q, scan}, qlen_dev, qlen_host, partial);
+    hipLaunchKernelGGL(k_scan_top_g<0>, dim3(1), dim3(SCAN_BLOCK), 0, L.stream, partial, nb);
+    hipLaunchKernelGGL((k_scan_apply_g<KeptValue, TileSink>), dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, L.stream,
+                       KeptValue{scan}, qlen_dev, qlen_host, partial, nb, TileSink{scan, tile_start, total_out});
+    return 3;
 }
 
 // ------------------------------------------------------------------ top-down expand
