@@ -425,8 +425,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is described "
-              "in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the search is built for one GPU, "
+              "and no sharded path exists to time on several", file=sys.stderr)
         sys.exit(2)
     if args.workload == "serve":
         serve_bench(args)
