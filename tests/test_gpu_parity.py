@@ -312,6 +312,10 @@ def test_config2_scale22_sampled_sources(orc):
                          (bfs.BFS_PARENT_MIN, 0)):
             p, d, _ = dg.run(s, parent_mode=pm, bu_head=head)
             check(orc, dg, s, p, d, pm == bfs.BFS_PARENT_MIN, ref)
+        # the large-graph defaults at this scale: ranked hub heads on the first
+        # bottom-up level and the hub pre-pass on top-down levels of 2^16+ edges
+        p, d, _ = dg.run(s, bu_head=3, td_prepass=1 << 16)
+        check(orc, dg, s, p, d, False, ref)
 
 
 def _progress(msg):
