@@ -98,10 +98,13 @@ typedef struct {
     double beta;           /* bottom-up -> top-down when n_f * beta < n (18)       */
     int32_t timing;        /* HIP events -> stats: 0 none, 1 around every kernel,
                               2 around the bottom-up sweeps only               */
-    int32_t bu_serial;     /* entries a lane scans alone before its wave helps (0 = default) */
-    int32_t grid_blocks;   /* cap on workgroups of grid-stride kernels (0 = default) */
-    int32_t td_claim;      /* ANY parents, top-down claim: 0 = atomic fetch-or on a
-                              claim bitmap, 1 = compare-and-swap on parent[]     */
+    int32_t bu_serial;     /* entries a lane scans alone before its wave helps
+                              (0 = default 16)                                   */
+    int32_t grid_blocks;   /* cap on workgroups of grid-stride kernels
+                              (0 = default 2048)                                 */
+    int32_t td_claim;      /* ANY parents, top-down claim: 0 = atomic fetch-or on
+                              the visited bitmap, 1 = compare-and-swap on
+                              parent[]                                           */
     int32_t small_edges;   /* top-down levels with at most this many frontier
                               edges run back to back inside one persistent
                               workgroup with no host round trip (0 = default
@@ -120,7 +123,9 @@ typedef struct {
                               0 (default) = 3 on a level entered from top-down
                               when the frontier bitmap (n/8 bytes) is larger
                               than the device's L2 cache, else 2; 1 = its first
-                              three row entries (MIN always uses these)        */
+                              three row entries (MIN always uses these).  3
+                              falls back to 2 on a graph without hubs (no
+                              degree threshold leaves fewer than 65536)        */
     int32_t td_prepass;    /* ANY parents (fetch-or claims), direction-optimizing:
                               a top-down level with at least this many frontier
                               edges first lets every unvisited vertex probe its
