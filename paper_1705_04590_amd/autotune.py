@@ -134,6 +134,15 @@ def tune(g, sources, k: int = 1, cache_path: str | None = None, reps: int = 3, v
     return result
 
 
+def cached(g, k: int, cache_path: str):
+    """The cached entry for graph g and batch size k on this device, or None (no search is run)."""
+    if not cache_path or not os.path.exists(cache_path):
+        return None
+    with open(cache_path) as f:
+        entry = json.load(f).get(_key(g, k))
+    return dict(entry, cached=True) if entry is not None else None
+
+
 def opts_from(result: dict, **extra):
     cfg = {k: result[k] for k in ("alpha", "beta", "bu_serial", "grid_blocks", "td_claim", "small_edges", "bu_head",
                                   "td_prepass") if k in result}

@@ -1,0 +1,286 @@
+"""GPU parity at the sizes and launch configurations the benchmark times.
+
+  * Kronecker scale 26: ten sources with the knobs the benchmark's autotuner
+    cached for this graph, minimum-id parents compared exactly with the
+    oracle and any-parent results checked by the BFS-tree invariants (which
+    fix every depth); the 64-source batch, every slice equal to the
+    single-source search, which the first check ties to the oracle.
+  * Kronecker scale 22: sixteen sources with its cached knobs, exactly.
+  * Kronecker scale 24, 64-source batch: every slice's depth and minimum
+    parent against the oracle.
+  * 4096 x 4096 grid, 64-source batch including the corner source: every
+    slice against the closed form (Manhattan depth; minimum parent up, else
+    left, else right, else down), no oracle run.
+  * The 12-graph serving set: a mixed stream whose every result equals the
+    stand-alone search, one result per graph equal to the oracle.
+
+Oracle calls run in a thread pool (the C oracle releases the GIL), so the
+per-test time stays inside the suite's limit.
+"""
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import graphgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1705_04590_amd as bfs  # noqa: E402
+from paper_1705_04590_amd import autotune, serve  # noqa: E402
+
+DEV = torch.device("cuda:0")
+FLAGS = bfs.BFS_GRAPH_SYMMETRIC | bfs.BFS_GRAPH_SORTED
+CACHE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1705_04590_amd",
+                     "autotune_cache.json")
+POOL = 12
+
+
+def progress(msg):
+    print(f"[{time.strftime('%H:%M:%S')}] {msg}", file=sys.__stderr__, flush=True)
+
+
+class Resident:
+    def __init__(self, off, cols):
+        self.off, self.cols, self.n = off, cols, off.size - 1
+        self.d_off = torch.from_numpy(off).to(DEV)
+        self.d_cols = torch.from_numpy(cols).to(DEV)
+        self.g = bfs.bfs_create_graph_csr(self.d_off, self.d_cols, FLAGS)
+        self.ws = None
+        self.par = torch.empty(self.n, dtype=torch.int32, device=DEV)
+        self.dep = torch.empty(self.n, dtype=torch.int32, device=DEV)
+
+    def tuned(self, k, **extra):
+        entry = autotune.cached(self.g, k, CACHE)
+        assert entry is not None, "no cached knobs for this graph: the benchmark's configuration is unknown"
+        return autotune.opts_from(entry, **extra)
+
+    def run(self, s, opts):
+        if self.ws is None:
+            self.ws = bfs.workspace(self.g, 1, DEV)
+        self.par.fill_(-7)
+        self.dep.fill_(-7)
+        bfs.bfs_run(self.g, int(s), self.par, self.dep, self.ws, opts)
+        torch.cuda.synchronize()
+        return self.par.cpu().numpy(), self.dep.cpu().numpy()
+
+    def close(self):
+        self.g.close()
+
+
+def oracle_min(orc, off, cols, sources):
+    with ThreadPoolExecutor(POOL) as ex:
+        return list(ex.map(lambda s: orc.bfs_min(off, cols, int(s)), sources))
+
+
+@pytest.fixture(scope="module")
+def kron26():
+    progress("scale 26: generating")
+    off, cols = graphgen.kronecker(26, seed=1)
+    r = Resident(off, cols)
+    yield r
+    r.close()
+    del r
+    torch.cuda.empty_cache()
+
+
+def test_scale26_tuned_knobs_ten_sources(orc, kron26):
+    r = kron26
+    srcs = [int(s) for s in graphgen.random_sources(r.off, 64, seed=2)[2:12]]
+    any_opts, min_opts = r.tuned(1), r.tuned(1, parent_mode=bfs.BFS_PARENT_MIN)
+    assert any_opts.grid_blocks == 1024
+    progress("scale 26: GPU searches")
+    results = []
+    for s in srcs:
+        pa, da = r.run(s, any_opts)
+        pm, dm = r.run(s, min_opts)
+        results.append((s, pa, da, pm, dm))
+    progress("scale 26: oracle and validator")
+
+    def check(item):
+        s, pa, da, pm, dm = item
+        rp, rd = orc.bfs_min(r.off, r.cols, s)
+        ok_min = np.array_equal(dm, rd) and np.array_equal(pm, rp)
+        ok_any = np.array_equal(da, rd) and orc.validate(r.off, r.cols, s, pa, da)[0] == "ok"
+        return s, ok_min, ok_any
+
+    with ThreadPoolExecutor(5) as ex:
+        for s, ok_min, ok_any in ex.map(check, results):
+            assert ok_min, f"source {s}: minimum-parent search differs from the oracle"
+            assert ok_any, f"source {s}: any-parent search fails the BFS-tree invariants"
+    progress("scale 26: done")
+
+
+def test_scale26_batch64_slices_equal_single_searches(kron26):
+    r = kron26
+    srcs = [int(s) for s in graphgen.random_sources(r.off, 64, seed=2)]
+    k, n = len(srcs), r.n
+    ws = bfs.workspace(r.g, k, DEV)
+    par = torch.empty(k * n, dtype=torch.int32, device=DEV)
+    dep = torch.empty(k * n, dtype=torch.int32, device=DEV)
+    progress("scale 26: 64-source batch")
+    bfs.bfs_run_multi(r.g, srcs, par, dep, ws, r.tuned(64, timing=0))
+    torch.cuda.synchronize()
+    del ws
+    single = r.tuned(1, parent_mode=bfs.BFS_PARENT_MIN)
+    sws = bfs.workspace(r.g, 1, DEV)
+    p1 = torch.empty(n, dtype=torch.int32, device=DEV)
+    d1 = torch.empty(n, dtype=torch.int32, device=DEV)
+    for j, s in enumerate(srcs):
+        bfs.bfs_run(r.g, s, p1, d1, sws, single)
+        assert torch.equal(dep[j * n:(j + 1) * n], d1), f"slice {j}: depth differs from bfs_run"
+        assert torch.equal(par[j * n:(j + 1) * n], p1), f"slice {j}: parent differs from bfs_run"
+    progress("scale 26: 64 slices equal")
+    del par, dep, sws
+
+
+def test_scale22_tuned_knobs_sixteen_sources(orc):
+    off, cols = graphgen.kronecker(22, seed=1)
+    r = Resident(off, cols)
+    srcs = [int(s) for s in graphgen.random_sources(off, 64, seed=2)[:16]]
+    refs = oracle_min(orc, off, cols, srcs)
+    any_opts, min_opts = r.tuned(1), r.tuned(1, parent_mode=bfs.BFS_PARENT_MIN)
+    items = []
+    for s, (rp, rd) in zip(srcs, refs):
+        pm, dm = r.run(s, min_opts)
+        assert np.array_equal(dm, rd) and np.array_equal(pm, rp), f"source {s}"
+        pa, da = r.run(s, any_opts)
+        assert np.array_equal(da, rd), f"source {s}"
+        items.append((s, pa, da))
+    with ThreadPoolExecutor(POOL) as ex:
+        for s, res in ex.map(lambda it: (it[0], orc.validate(off, cols, it[0], it[1], it[2])), items):
+            assert res[0] == "ok", (s, res)
+    r.close()
+
+
+def batch(r, srcs, opts=None):
+    k, n = len(srcs), r.n
+    ws = bfs.workspace(r.g, k, DEV)
+    par = torch.full((k * n,), -7, dtype=torch.int32, device=DEV)
+    dep = torch.full((k * n,), -7, dtype=torch.int32, device=DEV)
+    st = bfs.bfs_run_multi(r.g, srcs, par, dep, ws, opts or bfs.bfs_opts_default())
+    torch.cuda.synchronize()
+    del ws
+    out = par.cpu().numpy().reshape(k, n), dep.cpu().numpy().reshape(k, n), st
+    del par, dep
+    torch.cuda.empty_cache()
+    return out
+
+
+def test_scale24_batch64_every_slice_against_oracle(orc):
+    progress("scale 24: generating")
+    off, cols = graphgen.kronecker(24, seed=1)
+    r = Resident(off, cols)
+    srcs = [int(s) for s in graphgen.random_sources(off, 64, seed=2)]
+    progress("scale 24: batch")
+    p, d, st = batch(r, srcs)
+    r.close()
+    progress("scale 24: oracle, 64 sources")
+
+    def check(j):
+        rp, rd = orc.bfs_min(off, cols, srcs[j])
+        return j, np.array_equal(d[j], rd), np.array_equal(p[j], rp)
+
+    with ThreadPoolExecutor(POOL) as ex:
+        for j, ok_d, ok_p in ex.map(check, range(len(srcs))):
+            assert ok_d, f"slice {j} (source {srcs[j]}): depth differs from the oracle"
+            assert ok_p, f"slice {j} (source {srcs[j]}): minimum parent differs from the oracle"
+    progress("scale 24: done")
+
+
+def test_grid4096_batch64_closed_form():
+    H = W = 4096
+    off, cols = graphgen.grid2d(H, W)
+    r = Resident(off, cols)
+    srcs = [0] + [int(s) for s in graphgen.random_sources(off, 64, seed=3)[:63]]
+    progress("grid 4096^2: batch")
+    p, d, st = batch(r, srcs)
+    r.close()
+    assert st.levels == max(max(s // W, H - 1 - s // W) + max(s % W, W - 1 - s % W) for s in srcs) + 1
+    rr, cc = np.divmod(np.arange(H * W, dtype=np.int64), W)
+
+    def check(j):
+        s = srcs[j]
+        r0, c0 = divmod(s, W)
+        dist = np.abs(rr - r0) + np.abs(cc - c0)
+        par = np.where(rr > r0, (rr - 1) * W + cc,
+                       np.where(cc > c0, rr * W + cc - 1,
+                                np.where(cc < c0, rr * W + cc + 1, (rr + 1) * W + cc)))
+        par[s] = s
+        return j, np.array_equal(d[j], dist), np.array_equal(p[j], par)
+
+    with ThreadPoolExecutor(8) as ex:
+        for j, ok_d, ok_p in ex.map(check, range(len(srcs))):
+            assert ok_d, f"slice {j} (source {srcs[j]}): depth is not the Manhattan distance"
+            assert ok_p, f"slice {j} (source {srcs[j]}): parent is not the closed-form minimum"
+    progress("grid 4096^2: 64 slices match the closed form")
+
+
+SERVE_GRAPHS = [("kron", 14, 1), ("kron", 16, 1), ("kron", 18, 1), ("kron", 20, 1), ("kron", 22, 1),
+                ("kron", 24, 1), ("er", 20, 1), ("grid", 1024, 0), ("grid", 2048, 0), ("kron", 18, 2),
+                ("kron", 20, 2), ("kron", 22, 2)]
+
+
+def test_serving_twelve_graphs_mixed_stream(orc):
+    progress("serving: 12 graphs")
+    gs = []
+    for kind, p, seed in SERVE_GRAPHS:
+        if kind == "kron":
+            off, cols = graphgen.kronecker(p, 16, seed=seed)
+        elif kind == "er":
+            off, cols = graphgen.erdos_renyi(1 << p, 8.0, seed=seed)
+        else:
+            off, cols = graphgen.grid2d(p, p)
+        gs.append(Resident(off, cols))
+    rng = np.random.default_rng(12)
+    reqs = []
+    for gi in list(range(len(gs))) * 4 + list(rng.integers(0, len(gs), 24)):
+        srcs = graphgen.random_sources(gs[gi].off, 8, seed=int(rng.integers(0, 1 << 30)))
+        reqs.append((int(gi), int(srcs[0])))
+    reqs.append(reqs[5])   # a repeated query
+    order = rng.permutation(len(reqs))
+    srv = serve.Server(serve.bfs_server_opts_default(slots=4, max_batch=64, want_parent=1, hbm_budget=64 << 30))
+    gids = [srv.bfs_server_add_graph(x.g) for x in gs]
+    outs = []
+    for rid, i in enumerate(order):
+        gi, s = reqs[i]
+        n = gs[gi].n
+        d = np.full(n, -7, np.int32)
+        p = np.full(n, -7, np.int32)
+        srv.bfs_server_submit(gids[gi], s, rid, d, p)
+        outs.append((gi, s, p, d))
+    srv.bfs_server_drain()
+    st = srv.bfs_server_stats_get()
+    srv.bfs_server_destroy()
+    assert st["completed"] == len(reqs) and st["batches"] < len(reqs)
+    progress(f"serving: {len(reqs)} queries in {st['batches']} batches; comparing with bfs_run")
+    alone = {}
+    min_opts = bfs.bfs_opts_default(parent_mode=bfs.BFS_PARENT_MIN)
+    for gi, s, p, d in outs:
+        if (gi, s) not in alone:
+            alone[(gi, s)] = gs[gi].run(s, min_opts)
+        ap, ad = alone[(gi, s)]
+        assert np.array_equal(d, ad) and np.array_equal(p, ap), f"graph {gi} source {s}: differs alone and in the mix"
+    progress("serving: oracle sample")
+    sample = {}
+    for gi, s, p, d in outs:
+        sample.setdefault(gi, (s, p, d))
+
+    def check(gi):
+        s, p, d = sample[gi]
+        rp, rd = orc.bfs_min(gs[gi].off, gs[gi].cols, s)
+        return gi, np.array_equal(d, rd) and np.array_equal(p, rp)
+
+    with ThreadPoolExecutor(POOL) as ex:
+        for gi, ok in ex.map(check, sorted(sample)):
+            assert ok, f"graph {gi}: served result differs from the oracle"
+    for x in gs:
+        x.close()
+    progress("serving: done")
