@@ -233,7 +233,10 @@ bfs_status bfs_run(bfs_graph* g, int64_t source, const bfs_opts* opts, int32_t* 
  *                  j's parent array, identical to bfs_run with MIN parents
  *   d_depth        device int32[k*n]; row j is source j's depth array
  * Parents are always the minimum-id parents (BFS_PARENT_MIN); the graph
- * must be SYMMETRIC and SORTED.                                            */
+ * must be SYMMETRIC and SORTED.  Levels are kept in 16 bits: a batch whose
+ * search needs more than 65535 levels (some source has a vertex more than
+ * 65534 hops away, e.g. on a path of more than 65535 vertices) fails with
+ * BFS_E_UNSUPPORTED once it reaches that level; bfs_run has no such limit. */
 bfs_status bfs_run_multi(bfs_graph* g, const int64_t* h_sources, int k, const bfs_opts* opts, int32_t* d_parent,
                          int32_t* d_depth, void* d_workspace, size_t workspace_bytes, void* hip_stream,
                          bfs_stats* stats);

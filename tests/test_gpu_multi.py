@@ -160,3 +160,18 @@ def test_multi_long_rows_get_minimum_parents(orc):
     for direction in (0, 1):
         p, d, _ = mg.multi(srcs, dir=direction)
         check_all(orc, mg, srcs, p, d)
+
+
+def test_multi_level_cap_is_an_error():
+    """Levels are 16-bit in the batched search: a path of 70 000 vertices
+    searched from one end needs 70 000 levels, more than 65 535, and the call
+    fails with BFS_E_UNSUPPORTED; from the middle it needs 35 000 and passes."""
+    n = 70000
+    off, cols = graphgen.csr_from_edges(n, np.arange(n - 1), np.arange(1, n))
+    mg = MG(off, cols)
+    with pytest.raises(bfs.BfsError) as e:
+        mg.multi([0, 5], with_parent=False)
+    assert e.value.status == 8
+    p, d, st = mg.multi([n // 2], with_parent=True)
+    assert np.array_equal(d[0], np.abs(np.arange(n) - n // 2))
+    assert st.levels == n // 2 + 1
