@@ -53,26 +53,54 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def level_bytes(st: dict, n: int, wo: int):
-    """Algorithmic HBM bytes of every expansion launch, per level.
+WORK_TABLE = os.path.join(ROOT, "tests", "golden", "kron{scale}_work_model.json")
+
+
+def load_work_table(scale, edgefactor, seed, source_seed, n, nnz):
+    """The oracle's per-level work counts for this graph and source seed
+    (written by tests/golden/make_work_model.py, which runs only the CPU
+    oracle), keyed by source id; (None, reason) when no table matches."""
+    path = WORK_TABLE.format(scale=scale)
+    if not os.path.exists(path):
+        return None, f"no work table {os.path.relpath(path, ROOT)}"
+    doc = json.load(open(path))
+    gr = doc["graph"]
+    if (gr["scale"], gr["edgefactor"], gr["seed"], gr["n"], gr["nnz"], doc["source_seed"]) != \
+            (scale, edgefactor, seed, n, nnz, source_seed):
+        return None, "work table is for another graph or source seed"
+    return {"isolated": gr["isolated"], "rows": {r["source"]: r for r in doc["sources"]},
+            "path": os.path.relpath(path, ROOT)}, ""
+
+
+def level_bytes(st: dict, row: dict, n: int, wo: int, iso: int):
+    """Algorithmic HBM bytes of every expansion launch of one search, per level.
 
     top-down level : |F|(4 + 2 W_o) + D_F (4 column + 4 probe) + |N| (4 parent + 4 depth + 4 queue)
     bottom-up level: n/8 visited + 2 W_o |U| + 4 X + n/8 frontier + 8 |N| + n/8 next/visited
-    with F the frontier, D_F its edges, N the next frontier, U the unvisited
-    vertices that have edges (vertices without edges are never scanned) and
-    X the adjacency entries examined up to the first hit.
+                     (+ 8 per entry of the -1 fill of isolated and still unreached
+                     vertices, on the sweep that writes it)
+    F the frontier, D_F its edges, N the next frontier, U the unvisited
+    vertices that have edges, X the adjacency entries a row-order first-hit
+    scan examines (Alg. 2).  Every count comes from the oracle's work table
+    `row`; only the direction of each level is the library's, and the
+    library's own per-level counts must equal the table's.
     """
+    lv = row["levels"]
     L = len(st["level_dir"])
+    if st["levels"] != len(lv):
+        raise ValueError(f"source {row['source']}: {st['levels']} levels, the oracle has {len(lv)}")
     out = []
     for d in range(L):
-        nf, mf = st["level_nf"][d], st["level_mf"][d]
-        nn = st["level_nf"][d + 1] if d + 1 < L else 0
+        nf, mf, mu, u, x = lv[d]
+        if (st["level_nf"][d], st["level_mf"][d], st["level_mu"][d]) != (nf, mf, mu):
+            raise ValueError(f"source {row['source']} level {d}: library counts differ from the oracle's")
+        nn = lv[d + 1][0] if d + 1 < len(lv) else 0
         if st["level_dir"][d] == 0:
-            b = nf * (4 + 2 * wo) + mf * 8 + nn * 12 if mf > 0 else 0
-            out.append(("td_expand", b))
+            out.append(("td_expand", nf * (4 + 2 * wo) + mf * 8 + nn * 12 if mf > 0 else 0))
         else:
-            u, x = max(st["level_unvisited"][d] - st["isolated"], 0), st["level_examined"][d]
             b = 3 * (n / 8) + 2 * wo * u + 4 * x + 8 * nn
+            if st.get("fill_level") == d:
+                b += 8 * (iso + u - nn)
             out.append(("bu_sweep", b))
     return out
 
@@ -91,20 +119,60 @@ def read_traffic(kernel: str):
     return rec.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(off, cols, sources, m, max_seconds):
+def host_cpu():
+    """(model name, CPUs this process may run on, CPUs of the machine)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0)), os.cpu_count()
+
+
+def cpu_baseline(off, cols, sources, m, max_seconds, max_threads=16):
+    """The serial oracle (Alg. 1), built -O3 -march=native on this host.
+
+    latency: one thread pinned to one core, sources in order until the
+    budget is spent (at least one); throughput: one independent oracle search
+    per core at once (up to max_threads cores of this process's affinity
+    set), each from its own source, counted as queries/s."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
-    orc = oracle.load()
-    t_total, done = 0.0, 0
-    for s in sources:
+    orc = oracle.load_timing()
+    model, nproc, ncpu = host_cpu()
+    mask = os.sched_getaffinity(0)
+    core = min(mask)
+    os.sched_setaffinity(0, {core})
+    try:
+        t_total, done = 0.0, 0
+        for s in sources:
+            t0 = time.perf_counter()
+            orc.bfs(off, cols, int(s))
+            t_total += time.perf_counter() - t0
+            done += 1
+            if t_total >= max_seconds:
+                break
+    finally:
+        os.sched_setaffinity(0, mask)
+    threads = max(1, min(nproc, max_threads, len(sources)))
+    with ThreadPoolExecutor(threads) as ex:
         t0 = time.perf_counter()
-        orc.bfs(off, cols, int(s))
-        t_total += time.perf_counter() - t0
-        done += 1
-        if t_total >= max_seconds:
-            break
+        list(ex.map(lambda s: orc.bfs(off, cols, int(s)), sources[:threads]))
+        wall = time.perf_counter() - t0
     return {"value": m * done / t_total / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": f"{done} of the {len(sources)} sources, full graph, serial Alg. 1 oracle (one thread), "
-                      f"{t_total:.1f} s"}
+            "sample": f"{done} of the {len(sources)} sources one after another on one pinned core, full graph, "
+                      f"serial Alg. 1 oracle built -O3 -march=native, {t_total:.1f} s",
+            "search_s": round(t_total / done, 3),
+            "throughput": {"queries_per_s": round(threads / wall, 3), "gteps": round(m * threads / wall / 1e9, 4),
+                           "cores": threads,
+                           "sample": f"{threads} independent oracle searches at once, one per core, sources "
+                                     f"0..{threads - 1}, {wall:.1f} s"},
+            "host": {"cpu_model": model, "nproc": nproc, "cpu_count": ncpu}}
 
 
 SERVE_GRAPHS = [("kron14", "kron", 14, 1), ("kron16", "kron", 16, 1), ("kron18", "kron", 18, 1),
@@ -113,18 +181,14 @@ SERVE_GRAPHS = [("kron14", "kron", 14, 1), ("kron16", "kron", 16, 1), ("kron18",
                 ("kron18_s2", "kron", 18, 2), ("kron20_s2", "kron", 20, 2), ("kron22_s2", "kron", 22, 2)]
 
 
-def serve_bench(args):
-    """Served queries over 12 resident graphs: Poisson arrivals, continuous batching vs one query per launch."""
-    import numpy as np
+def serve_graphs(dev):
+    """The 12 resident graphs of the serving configuration, with 256 query sources each (seed 6)."""
     import torch
 
     import graphgen
     import paper_1705_04590_amd as bfs
-    from paper_1705_04590_amd import serve
 
-    dev = torch.device("cuda:0")
     graphs, keep = [], []
-    t0 = time.time()
     for name, kind, p, seed in SERVE_GRAPHS:
         if kind == "kron":
             off, cols = graphgen.kronecker(p, 16, seed=seed)
@@ -137,8 +201,20 @@ def serve_bench(args):
         srcs = graphgen.random_sources(off, 256, seed=6)
         graphs.append((name, g, srcs, off.size - 1, int(off[-1])))
         keep.append((d_off, d_cols))
-    log(f"[serve] {len(graphs)} graphs resident in {time.time() - t0:.1f}s: " +
-        ", ".join(f"{x[0]}(n={x[3]})" for x in graphs))
+    return graphs, keep
+
+
+def serve_measure(graphs, rates, seconds, max_requests, slots, budget_gib):
+    """Poisson arrivals (seed 6) at rates given as multiples of the one-query-per-launch
+    capacity; each rate served twice: by continuous batching (up to 64 same-graph
+    queries per batch, `slots` batches in flight) and by one query per launch
+    (one slot, batches of one).  Returns (capacity one-per-launch, capacity
+    batched, per-rate rows)."""
+    import numpy as np
+    import torch
+
+    from paper_1705_04590_amd import serve
+
     rng = np.random.default_rng(6)
 
     def stream(m, rate):
@@ -148,8 +224,8 @@ def serve_bench(args):
         src = np.array([graphs[g][2][rng.integers(0, 256)] for g in gi], dtype=np.int64)
         return t, gi, src
 
-    def run(t, gi, src, slots, max_batch):
-        o = serve.bfs_server_opts_default(slots=slots, max_batch=max_batch, hbm_budget=args.serve_budget_gib << 30)
+    def run(t, gi, src, nslots, max_batch):
+        o = serve.bfs_server_opts_default(slots=nslots, max_batch=max_batch, hbm_budget=budget_gib << 30)
         srv = serve.Server(o)
         for x in graphs:
             srv.bfs_server_add_graph(x[1])
@@ -161,28 +237,27 @@ def serve_bench(args):
         log(f"[serve]   server done: {free / 2**30:.1f} of {total / 2**30:.1f} GiB free")
         return st
 
-    m = args.serve_requests
+    m = max_requests
     # capacity of one query per launch: everything arrives at once, FIFO, one
-    # slot, batches of one (bfs_run); a short pilot sizes the measured run to
-    # about `serve_seconds`
+    # slot, batches of one (bfs_run); a short pilot sizes the measured run
     t, gi, src = stream(m, 1e9)
     pilot = run(np.zeros(32), gi[:32], src[:32], 1, 1)["queries_per_s"]
-    m1 = int(min(m, max(64, pilot * args.serve_seconds)))
+    m1 = int(min(m, max(64, pilot * seconds)))
     log(f"[serve] pilot {pilot:.0f} q/s -> {m1} queries for the one-per-launch capacity run")
     cap1 = run(np.zeros(m1), gi[:m1], src[:m1], 1, 1)["queries_per_s"]
-    capb = run(np.zeros(m), gi, src, args.serve_slots, 64)["queries_per_s"]
+    capb = run(np.zeros(m), gi, src, slots, 64)["queries_per_s"]
     log(f"[serve] capacity: one query per launch {cap1:.0f} q/s, batched {capb:.0f} q/s")
     rows = []
-    for f in args.serve_rates:
+    for f in rates:
         rate = f * cap1
-        # arrivals span about serve_seconds; the one-per-launch server needs
-        # about serve_seconds * max(f, 1) to work through them
-        mr = int(min(m, max(64, rate * args.serve_seconds / max(f, 1.0))))
+        # arrivals span about `seconds`; the one-per-launch server needs about
+        # seconds * max(f, 1) to work through them
+        mr = int(min(m, max(64, rate * seconds / max(f, 1.0))))
         t, gi, src = stream(mr, rate)
         single = run(t, gi, src, 1, 1)
         log(f"[serve] {f:>4}x ({mr} queries at {rate:.0f}/s): one-per-launch {single['queries_per_s']:.0f} q/s "
             f"p50 {single['p50_us'] / 1e3:.2f} ms p99 {single['p99_us'] / 1e3:.2f} ms")
-        batched = run(t, gi, src, args.serve_slots, 64)
+        batched = run(t, gi, src, slots, 64)
         rows.append({"rate_x_single_capacity": f, "offered_qps": round(rate, 1), "requests": mr,
                      "batched": {k: round(batched[k], 2) for k in ("queries_per_s", "p50_us", "p99_us",
                                                                     "mean_batch", "max_inflight")},
@@ -191,6 +266,21 @@ def serve_bench(args):
         log(f"[serve] {f:>4}x: batched {batched['queries_per_s']:.0f} q/s p50 {batched['p50_us'] / 1e3:.2f} ms "
             f"p99 {batched['p99_us'] / 1e3:.2f} ms (batch {batched['mean_batch']:.1f}, inflight "
             f"{batched['max_inflight']})")
+    return cap1, capb, rows
+
+
+def serve_bench(args):
+    """Served queries over 12 resident graphs: Poisson arrivals, continuous batching vs one query per launch."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    graphs, keep = serve_graphs(dev)
+    log(f"[serve] {len(graphs)} graphs resident in {time.time() - t0:.1f}s: " +
+        ", ".join(f"{x[0]}(n={x[3]})" for x in graphs))
+    cap1, capb, rows = serve_measure(graphs, args.serve_rates, args.serve_seconds, args.serve_requests,
+                                     args.serve_slots, args.serve_budget_gib)
+    m = args.serve_requests
     out = {"metric": "served BFS queries/s and p50/p99 latency, 12 resident graphs, Poisson arrivals",
            "value": round(capb, 1), "unit": "queries/s", "n_gpus": 1, "steps": m, "warmup": 0,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
@@ -419,6 +509,11 @@ def main():
                     help="do not record HIP events around the bottom-up sweeps (no roofline entry)")
     ap.add_argument("--batched-reps", type=int, default=3,
                     help="timed repetitions of the 64-source batched search (0 = skip)")
+    ap.add_argument("--no-serve", action="store_true", help="leave the served leg out of the headline line")
+    ap.add_argument("--line-serve-rates", type=float, nargs="+", default=[1.0, 3.0],
+                    help="offered rates (x the one-query-per-launch capacity) of the headline line's served leg")
+    ap.add_argument("--line-serve-seconds", type=float, default=3.0,
+                    help="approximate span of each run of the headline line's served leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run three 1 GiB device-to-device copies (the plain copy kernel "
                          "that scales FETCH_SIZE / WRITE_SIZE counters)")
@@ -452,6 +547,10 @@ def main():
     m = nnz // 2
     log(f"[bench] n={n} nnz={nnz} m={m} generated in {time.time() - t0:.1f}s")
     sources = graphgen.random_sources(off, args.nsources, seed=args.source_seed)
+    nsrc = len(sources)
+    table, table_note = load_work_table(args.scale, args.edgefactor, args.seed, args.source_seed, n, nnz)
+    if table is None:
+        log(f"[bench] {table_note}: no roofline entry")
 
     dev = torch.device("cuda:0")
     use32 = nnz < 2 ** 31 and args.scale < 22
@@ -468,14 +567,17 @@ def main():
     log(f"[bench] graph resident ({(d_off.numel() * d_off.element_size() + nnz * 4) / 2**30:.2f} GiB), "
         f"workspace {ws.numel() / 2**30:.2f} GiB; warmup {args.warmup}")
 
-    def timed_steps(o):
+    # step i searches from sources[i mod 64]; the warm-up searches take the
+    # sources from the end of the list, so K < 64 timed steps still time K
+    # distinct sources
+    def timed_steps(o, steps):
         for i in range(args.warmup):
-            bfs.bfs_run(g, int(sources[i % len(sources)]), parent, depth, ws, o, stream)
+            bfs.bfs_run(g, int(sources[(nsrc - 1 - i) % nsrc]), parent, depth, ws, o, stream)
         torch.cuda.synchronize()
         sts = []
         t_begin = time.perf_counter()
-        for i in range(args.steps):
-            sts.append(bfs.bfs_run(g, int(sources[i % len(sources)]), parent, depth, ws, o, stream))
+        for i in range(steps):
+            sts.append(bfs.bfs_run(g, int(sources[i % nsrc]), parent, depth, ws, o, stream))
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_begin
         # the per-level records are turned into dicts after the clock stops
@@ -494,14 +596,14 @@ def main():
             f"engine={tuned.get('small_edges', 0)} ({tuned['default_ms']:.3f} -> {tuned['tuned_ms']:.3f} ms on "
             f"tuning sources)")
         log(f"[bench] timing {args.steps} steps with alpha={args.alpha} beta={args.beta} (defaults)")
-        d_stats, d_elapsed = timed_steps(opts)
+        d_stats, d_elapsed = timed_steps(opts, args.steps)
         default_params = {"value": round(m * args.steps / d_elapsed / 1e9, 3), "alpha": args.alpha,
                           "beta": args.beta, "ms_per_step": round(d_elapsed / args.steps * 1e3, 4)}
         log(f"[bench] defaults: {default_params['value']} GTEPS")
         opts = autotune.opts_from(tuned, dir=0, parent_mode=opts.parent_mode, timing=opts.timing)
 
     log(f"[bench] timing {args.steps} steps (alpha={opts.alpha} beta={opts.beta})")
-    stats, elapsed = timed_steps(opts)
+    stats, elapsed = timed_steps(opts, args.steps)
     gteps = m * args.steps / elapsed / 1e9
     per_source_ms = [s["total_ms"] for s in stats]
     log(f"[bench] {args.steps} searches in {elapsed:.3f}s -> {gteps:.2f} GTEPS "
@@ -514,14 +616,18 @@ def main():
         for s in stats:
             for k, v in s["kernel_ms"].items():
                 kernel_totals[k] = kernel_totals.get(k, 0.0) + v
+        log(f"[bench] kernel ms over timed steps: " +
+            ", ".join(f"{k}={v:.2f}" for k, v in sorted(kernel_totals.items(), key=lambda x: -x[1]) if v))
+    if not args.no_timing and table is not None:
         # events bracket only the bottom-up sweeps (timing mode 2), the
         # dominant kernel of this workload (see the kernel-trace profile)
         dom = "bu_sweep"
         wo = d_off.element_size()
         nbytes, launches, ms = 0.0, 0, 0.0
-        for s in stats:
-            for d, (kind, b) in enumerate(level_bytes(s, n, wo)):
-                if kind == dom and (kind != "td_expand" or s["level_mf"][d] > 0):
+        for i, s in enumerate(stats):
+            row = table["rows"][int(sources[i % nsrc])]
+            for d, (kind, b) in enumerate(level_bytes(s, row, n, wo, table["isolated"])):
+                if kind == dom:
                     nbytes += b
                     launches += 1
                     ms += s["level_ms"][d]
@@ -532,20 +638,45 @@ def main():
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                         "launches": launches, "avg_launch_us": round(avg_s * 1e6, 2),
-                        "alg_bytes_per_launch": round(nbytes / launches)}
-        log(f"[bench] kernel ms over timed steps: " +
-            ", ".join(f"{k}={v:.2f}" for k, v in sorted(kernel_totals.items(), key=lambda x: -x[1]) if v))
+                        "alg_bytes_per_launch": round(nbytes / launches),
+                        "alg_bytes_from": f"oracle work table {table['path']} (counts of the timed sources; "
+                                          "the -1 fill counted on the sweep that writes it)",
+                        "sources_timed": min(args.steps, nsrc)}
+
+    # ---- every source once (outside the K-step timed region)
+    all_sources = None
+    if args.steps < nsrc:
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        for s_ in sources:
+            bfs.bfs_run(g, int(s_), parent, depth, ws, opts, stream)
+        torch.cuda.synchronize()
+        t_all = time.perf_counter() - t_a
+        all_sources = {"sources": nsrc, "gteps": round(m * nsrc / t_all / 1e9, 3),
+                       "ms_per_search": round(t_all / nsrc * 1e3, 4)}
+        log(f"[bench] all {nsrc} sources once: {m * nsrc / t_all / 1e9:.2f} GTEPS")
 
     batched = None
     if args.batched_reps > 0:
-        k = min(64, len(sources))
+        from paper_1705_04590_amd import autotune
+        k = min(64, nsrc)
         log(f"[bench] batched: {k} sources per bfs_run_multi, {args.batched_reps} timed reps")
+        # the same k sources one at a time with minimum parents (the batch's
+        # parent mode), with the knobs tuned for single searches
+        mino = (autotune.opts_from(tuned, dir=0, parent_mode=1, timing=0) if tuned is not None
+                else bfs.bfs_opts_default(parent_mode=1, alpha=args.alpha, beta=args.beta))
+        bfs.bfs_run(g, int(sources[0]), parent, depth, ws, mino, stream)
+        torch.cuda.synchronize()
+        t_s = time.perf_counter()
+        for s_ in sources[:k]:
+            bfs.bfs_run(g, int(s_), parent, depth, ws, mino, stream)
+        torch.cuda.synchronize()
+        single_min_qps = k / (time.perf_counter() - t_s)
         wsm = bfs.workspace(g, k, dev)
         bpar = torch.empty(k * n, dtype=torch.int32, device=dev)
         bdep = torch.empty(k * n, dtype=torch.int32, device=dev)
         mopts = bfs.bfs_opts_default(alpha=args.alpha, beta=args.beta, timing=0)
         if tuned is not None:
-            from paper_1705_04590_amd import autotune
             mt = autotune.tune(g, graphgen.random_sources(off, k, seed=99), k=k, cache_path=args.tune_cache,
                                force=args.retune)
             mopts = autotune.opts_from(mt, timing=0)
@@ -558,12 +689,15 @@ def main():
             bfs.bfs_run_multi(g, sources[:k], bpar, bdep, wsm, mopts, stream)
         torch.cuda.synchronize()
         batch_s = (time.perf_counter() - t_b) / args.batched_reps
-        single_qps = args.steps / elapsed
+        single_any_qps = args.steps / elapsed
         batched = {"sources_per_batch": k, "batch_ms": round(batch_s * 1e3, 3),
-                   "queries_per_s": round(k / batch_s, 1), "single_source_queries_per_s": round(single_qps, 1),
-                   "speedup_vs_single": round(k / batch_s / single_qps, 3), "parent_mode": "min"}
+                   "queries_per_s": round(k / batch_s, 1), "parent_mode": "min",
+                   "single_source_min_queries_per_s": round(single_min_qps, 1),
+                   "speedup_vs_single_min": round(k / batch_s / single_min_qps, 3),
+                   "single_source_any_queries_per_s": round(single_any_qps, 1),
+                   "speedup_vs_single_any": round(k / batch_s / single_any_qps, 3)}
         log(f"[bench] batched: {batch_s * 1e3:.2f} ms per {k}-source batch -> {k / batch_s:.1f} queries/s "
-            f"(single-source: {single_qps:.1f} queries/s)")
+            f"(single-source: {single_min_qps:.1f} q/s minimum parents, {single_any_qps:.1f} q/s any parents)")
         del wsm, bpar, bdep
         torch.cuda.empty_cache()
 
@@ -576,10 +710,26 @@ def main():
         del src_t, dst_t
         log("[bench] copy calibration: 3 x 1 GiB device copies done")
 
+    served = None
+    if not args.no_serve:
+        t0 = time.time()
+        sgraphs, keep = serve_graphs(dev)
+        log(f"[bench] serving leg: {len(sgraphs)} graphs resident in {time.time() - t0:.1f}s")
+        cap1, capb, rows = serve_measure(sgraphs, args.line_serve_rates, args.line_serve_seconds,
+                                         args.serve_requests, args.serve_slots, args.serve_budget_gib)
+        served = {"graphs": len(sgraphs), "capacity_one_query_per_launch_qps": round(cap1, 1),
+                  "capacity_batched_qps": round(capb, 1), "rates": rows}
+        for x in sgraphs:
+            x[1].close()
+        del keep, sgraphs
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"[bench] CPU oracle baseline (budget {args.cpu_seconds}s)")
+        log(f"[bench] CPU oracle baseline (latency budget {args.cpu_seconds}s, then one search per core)")
         cpu = cpu_baseline(off, cols, sources, m, args.cpu_seconds)
+        log(f"[bench] CPU: {cpu['value']:.4f} GTEPS on one core, {cpu['throughput']['queries_per_s']:.3f} q/s on "
+            f"{cpu['throughput']['cores']} cores ({cpu['host']['cpu_model']})")
 
     out = {
         "metric": METRIC, "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
@@ -587,7 +737,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"kronecker_s{args.scale}_ef{args.edgefactor}_single_source_{args.dir}",
                    "scale": args.scale, "edgefactor": args.edgefactor, "n": n, "nnz": nnz, "m_undirected": m,
-                   "sources": len(sources), "offsets": "int32" if use32 else "int64",
+                   "sources": nsrc, "sources_timed": min(args.steps, nsrc),
+                   "offsets": "int32" if use32 else "int64",
                    "parent_mode": args.parent_mode, "alpha": opts.alpha, "beta": opts.beta,
                    "bu_serial": opts.bu_serial or 16, "grid_blocks": opts.grid_blocks or 2048,
                    "td_claim": "cas" if opts.td_claim == 1 else "fetch_or",
@@ -599,12 +750,13 @@ def main():
                    "kernel_ms_total": {k: round(v, 3) for k, v in kernel_totals.items() if v}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "all_sources": all_sources,
         "batched": batched,
+        "served": served,
         "default_params": default_params,
     }
     print(json.dumps(out), flush=True)
     g.close()
-
 
 if __name__ == "__main__":
     main()

@@ -35,14 +35,26 @@ VALIDATE_CODES = {
 }
 
 
-def build(defines=(), out_path: str | None = None) -> str:
+def build(defines=(), out_path: str | None = None, opt=("-O2",)) -> str:
     """Compile the oracle with gcc -O2 (``defines`` is for planted-mistake tests)."""
     out = out_path or _LIB_PATH
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC] + [f"-D{d}" for d in defines]
+    cmd = ["gcc", *opt, "-shared", "-fPIC", "-o", tmp, _SRC] + [f"-D{d}" for d in defines]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
     return out
+
+
+_TIMING_PATH = os.path.join(_HERE, "liboracle_native.so")
+
+
+def load_timing():
+    """The same oracle source built for timing on this machine (gcc -O3 -march=native), loaded.
+
+    Only the benchmark's CPU-baseline leg uses it; it is rebuilt on every call
+    so that it is native to the host that runs it."""
+    build(out_path=_TIMING_PATH, opt=("-O3", "-march=native"))
+    return Oracle(_bind(ctypes.CDLL(_TIMING_PATH)))
 
 
 def _bind(lib):
