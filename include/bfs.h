@@ -272,6 +272,27 @@ bfs_status bfs_block_bu(bfs_graph* g, const uint64_t* d_fbits, uint64_t* d_compl
                         int64_t row_hi, int32_t* d_out_rows, int32_t* d_out_parents, int64_t* d_nout,
                         void* d_workspace, size_t workspace_bytes, void* hip_stream);
 
+/* Allocation-free variant of bfs_block_td, for callers that cannot
+ * allocate device memory: code being captured into a HIP graph, tight
+ * serving loops, harnesses that forbid hipMalloc.  The operation, the
+ * arguments it shares with bfs_block_td and the outputs are the same; the
+ * workspace is a file-scope device array of the library (64 MiB on every
+ * device the library runs on, held until the process ends) instead of a
+ * caller buffer, and the call allocates nothing.
+ *   - A block whose workspace (bfs_workspace_bytes) exceeds 64 MiB is
+ *     rejected with BFS_E_BUDGET before any launch.
+ *   - The block's device must be the current device (BFS_E_INVALID_ARG).
+ *   - Every call on one device shares that device's array and leaves its
+ *     contents to the next call.  Calls that overlap on one device (on
+ *     streams not ordered with each other, or from several threads at once)
+ *     race and give wrong results: order them, e.g. on one stream.
+ *   - The first call on a device, the call after a failed one and a call on
+ *     a block whose workspace layout differs from the previous call's clear
+ *     the part of the array they use with a kernel before the search.
+ * Asynchronous on hip_stream.                                              */
+bfs_status bfs_block_td_noalloc(bfs_graph* g, const int32_t* d_frontier, int64_t nf, int32_t* d_out_rows,
+                                int32_t* d_out_parents, int64_t* d_nout, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,7 +31,7 @@ STATUS_NAMES = {0: "BFS_OK", 1: "BFS_E_INVALID_ARG", 2: "BFS_E_OUT_OF_RANGE", 3:
                 8: "BFS_E_UNSUPPORTED"}
 EXPORTED = ["bfs_opts_default", "bfs_last_error", "bfs_status_string", "bfs_create_graph_csr",
             "bfs_create_graph_dcsc", "bfs_destroy_graph", "bfs_workspace_bytes", "bfs_run", "bfs_run_multi",
-            "bfs_block_td", "bfs_block_bu"]
+            "bfs_block_td", "bfs_block_bu", "bfs_block_td_noalloc"]
 
 
 class BfsError(RuntimeError):
@@ -106,8 +106,9 @@ def lib():
         L.bfs_block_td.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
         L.bfs_block_bu.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int64, _vp, _vp, _vp, _vp,
                                    ctypes.c_size_t, _vp]
+        L.bfs_block_td_noalloc.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
         for name in ("bfs_create_graph_csr", "bfs_create_graph_dcsc", "bfs_run", "bfs_run_multi", "bfs_block_td",
-                     "bfs_block_bu"):
+                     "bfs_block_bu", "bfs_block_td_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -263,6 +264,16 @@ def bfs_block_td(g: Graph, frontier: torch.Tensor, out_rows: torch.Tensor, out_p
                               _dev(out_parents, torch.int32, "out_parents", g.nrows),
                               _dev(nout, torch.int64, "nout", 1), _dev(ws, torch.uint8, "workspace"), ws.numel(),
                               _stream(stream)), "bfs_block_td")
+
+
+def bfs_block_td_noalloc(g: Graph, frontier: torch.Tensor, out_rows: torch.Tensor, out_parents: torch.Tensor,
+                         nout: torch.Tensor, stream=None):
+    """bfs_block_td without a caller workspace: the library's static device array is used (asynchronous)."""
+    nf = frontier.numel()
+    _check(lib().bfs_block_td_noalloc(g.handle, _opt_ptr(frontier, torch.int32, "frontier"), nf,
+                                      _dev(out_rows, torch.int32, "out_rows", g.nrows),
+                                      _dev(out_parents, torch.int32, "out_parents", g.nrows),
+                                      _dev(nout, torch.int64, "nout", 1), _stream(stream)), "bfs_block_td_noalloc")
 
 
 def bfs_block_bu(g: Graph, fbits: torch.Tensor, completed: torch.Tensor, row_lo: int, row_hi: int,

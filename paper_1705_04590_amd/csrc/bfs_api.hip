@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -884,6 +885,28 @@ int64_t graph_vertices(const bfs_graph* g) { return (g && g->kind == KIND_CSR) ?
 void set_last_error(const char* msg) { g_err = msg ? msg : ""; }
 }  // namespace bfsk
 
+// ---------------------------------------------------------- allocation-free block top-down
+// bfs_block_td_noalloc works in this file-scope device array instead of a
+// caller workspace.  Host code never passes `scratch` itself to a kernel (its
+// host-side name is not a device address): the device address is looked up
+// once per device with hipGetSymbolAddress and kept in g_na[device].ptr.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+struct NoAllocDevice {
+    bool ready = false;       // ptr looked up
+    void* ptr = nullptr;      // device address of `scratch` on this device
+    bool zeroed = false;      // the accumulator regions of `last` hold zeros
+    BlockLayout last{};       // layout of the previous call on this device
+};
+std::mutex g_na_mu;
+NoAllocDevice g_na[NOALLOC_MAX_DEVICES];
+
+bool same_layout(const BlockLayout& a, const BlockLayout& b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
+}  // namespace
+
 // ================================================================== C ABI
 extern "C" {
 
@@ -1167,6 +1190,51 @@ bfs_status bfs_block_td(bfs_graph* g, const int32_t* d_frontier, int64_t nf, int
     launch_clear_words(L, W.header, 8);
     launch_block_td(L, block_args(g), d_frontier, nf, d_out_rows, d_out_parents, d_nout, W);
     HIP_TRY(hipGetLastError());
+    return BFS_OK;
+}
+
+bfs_status bfs_block_td_noalloc(bfs_graph* g, const int32_t* d_frontier, int64_t nf, int32_t* d_out_rows,
+                                int32_t* d_out_parents, int64_t* d_nout, void* hip_stream) {
+    if (!g || g->kind != KIND_DCSC) return fail(BFS_E_INVALID_ARG, "graph handle is not a DCSC block");
+    if (nf < 0 || nf > g->ncols) return fail(BFS_E_INVALID_ARG, "nf=%lld outside [0, ncols]", (long long)nf);
+    if ((nf > 0 && !d_frontier) || !d_out_rows || !d_out_parents || !d_nout)
+        return fail(BFS_E_INVALID_ARG, "NULL frontier or output");
+    const BlockLayout Lo = block_layout(g);
+    if (Lo.total > NOALLOC_SCRATCH_BYTES)
+        return fail(BFS_E_BUDGET, "block needs %zu bytes of scratch, the static array holds %zu", Lo.total,
+                    NOALLOC_SCRATCH_BYTES);
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != g->device) return fail(BFS_E_INVALID_ARG, "the block lives on device %d, device %d is current",
+                                      g->device, dev);
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(BFS_E_UNSUPPORTED, "device %d: too many devices", dev);
+    std::lock_guard<std::mutex> lock(g_na_mu);
+    NoAllocDevice& D = g_na[dev];
+    if (!D.ready) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || (uintptr_t)p % ALIGN) return fail(BFS_E_HIP, "scratch array has no usable device address");
+        D.ptr = p;
+        D.ready = true;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    Launch L{st, 2048};
+    // the accumulator, occupied and frontier-mark regions must hold zeros;
+    // a call leaves them zeroed at its own layout's offsets, so a different
+    // layout (another block shape), the first call, or a failed call clears
+    // the whole range this layout uses, with a kernel
+    const bool need_clear = !D.zeroed || !same_layout(D.last, Lo);
+    D.zeroed = false;   // until this call has been issued completely
+    if (need_clear) {
+        launch_clear_words(L, (uint64_t*)D.ptr, (int64_t)(Lo.total / sizeof(uint64_t)));
+        HIP_TRY(hipGetLastError());
+    }
+    const BlockWs W = block_ws(g, (char*)D.ptr);
+    launch_clear_words(L, W.header, 8);
+    launch_block_td(L, block_args(g), d_frontier, nf, d_out_rows, d_out_parents, d_nout, W);
+    HIP_TRY(hipGetLastError());
+    D.last = Lo;
+    D.zeroed = true;
     return BFS_OK;
 }
 
