@@ -104,7 +104,17 @@ typedef struct {
                               (0 = default 2048)                                 */
     int32_t td_claim;      /* ANY parents, top-down claim: 0 = atomic fetch-or on
                               the visited bitmap, 1 = compare-and-swap on
-                              parent[]                                           */
+                              parent[], 2 = benign race (Section 5.2): no
+                              atomic test, every thread that saw the child
+                              unvisited writes its parent (several may; the
+                              repeats are counted in bfs_stats.td_duplicates)
+                              and sets its visited bit with an atomic whose
+                              result it does not wait for.  Such a level
+                              queues nothing: its next frontier is the exact
+                              bitmap of new vertices, so depths, frontier
+                              sizes and edge counts stay exact and parents
+                              valid.  Small levels run by the persistent
+                              engine keep exact claims                          */
     int32_t small_edges;   /* top-down levels with at most this many frontier
                               edges run back to back inside one persistent
                               workgroup with no host round trip (0 = default
@@ -133,20 +143,43 @@ typedef struct {
                               hits; the edge pass then finds them visited.
                               Needs hub ranks.  0 = default (2^24), negative =
                               never                                            */
-    int32_t reserved[3];
+    int32_t bu_segments;   /* bottom-up levels in column blocks (Alg. 4's
+                              sub-steps, Fig. 1, inside one device): 0 (default)
+                              = one sweep that scans every row to its first
+                              frontier entry; S = 1..8 = the sweep probes only
+                              the row heads, then S sub-steps, one per column
+                              segment of about n/S ids in ascending order, scan
+                              the remaining rows over that segment's entries,
+                              so each sub-step probes only its slice (n/(8S)
+                              bytes) of the frontier bitmap.  Rows are sorted,
+                              so the first hit is the same and minimum parents
+                              stay exact                                        */
+    int32_t reserved[2];
 } bfs_opts;
 
 typedef struct {
     int32_t levels;                 /* levels expanded (last one finds nothing)     */
     int32_t td_levels, bu_levels;
-    int32_t pad0;
+    int32_t fill_level;             /* bfs_run: where the -1 of the vertices not
+                                       reached was written: -1 by the
+                                       initialisation before level 0, d >= 0
+                                       by the expansion of level d (its
+                                       bottom-up sweep, or the hub pre-pass of a
+                                       top-down level), -2 by a pass after the
+                                       last level; -1 for bfs_run_multi       */
     int64_t reached;                /* vertices with depth >= 0                      */
     int64_t isolated;               /* symmetric graphs: vertices without entries
                                        (never scanned: they start out visited);
                                        0 for graphs not marked SYMMETRIC           */
     int64_t edges_examined;         /* adjacency entries examined (top-down: all
                                        entries of the frontier; bottom-up: entries
-                                       up to and including the first hit)          */
+                                       up to and including the first hit).  Not
+                                       the algorithmic byte count: any-parent
+                                       bottom-up levels probe hub neighbours
+                                       before the row, so this differs from the
+                                       row-order scan of Alg. 2 that the byte
+                                       model uses; the benchmark takes that scan
+                                       from the oracle's work table instead     */
     double total_ms;                /* host wall time of the call                    */
     int64_t launches[BFS_KERNEL_KINDS];
     double kernel_ms[BFS_KERNEL_KINDS]; /* summed HIP-event time (timing mode only)  */
@@ -161,6 +194,11 @@ typedef struct {
     int64_t level_unvisited[BFS_STATS_MAX_LEVELS];
     int64_t level_examined[BFS_STATS_MAX_LEVELS];
     float level_ms[BFS_STATS_MAX_LEVELS];
+    /* td_claim = 2: children taken by per-level top-down expansions (every
+     * take, with the hub pre-pass's), and how many of them repeat a child
+     * already taken at the same level                                       */
+    int64_t td_claims;
+    int64_t td_duplicates;
 } bfs_stats;
 
 typedef struct bfs_graph bfs_graph;
@@ -259,6 +297,19 @@ bfs_status bfs_run_multi(bfs_graph* g, const int64_t* h_sources, int k, const bf
 bfs_status bfs_block_td(bfs_graph* g, const int32_t* d_frontier, int64_t nf, int32_t* d_out_rows,
                         int32_t* d_out_parents, int64_t* d_nout, void* d_workspace, size_t workspace_bytes,
                         void* hip_stream);
+
+/* How bfs_block_td (and bfs_block_td_noalloc) unite the frontier's columns
+ * (Section 5.2 weighs a sparse accumulator against a heap-based merge):
+ *   0  (default) by density: when |F| times the block's mean column length
+ *      is at most 8192, one workgroup sorts the columns' (row, parent)
+ *      pairs in LDS and keeps each row's smallest parent; when the columns
+ *      turn out to hold more than 8192 entries, or the frontier is denser,
+ *      the sparse accumulator runs (its ordered pass reads nrows/64 words)
+ *   1  the sorted union whenever the entries fit (else the accumulator)
+ *  -1  the accumulator only
+ * The output is the same in every mode.  Returns BFS_E_INVALID_ARG for a
+ * handle that is not a DCSC block or a mode outside [-1, 1].               */
+bfs_status bfs_block_set_union(bfs_graph* g, int mode);
 
 /* Bottom-up local discovery on a DCSC block, one sub-step (Alg. 4): every
  * row r in [row_lo, row_hi) whose completed bit is 0 scans its columns in

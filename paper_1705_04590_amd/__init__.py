@@ -31,7 +31,7 @@ STATUS_NAMES = {0: "BFS_OK", 1: "BFS_E_INVALID_ARG", 2: "BFS_E_OUT_OF_RANGE", 3:
                 8: "BFS_E_UNSUPPORTED"}
 EXPORTED = ["bfs_opts_default", "bfs_last_error", "bfs_status_string", "bfs_create_graph_csr",
             "bfs_create_graph_dcsc", "bfs_destroy_graph", "bfs_workspace_bytes", "bfs_run", "bfs_run_multi",
-            "bfs_block_td", "bfs_block_bu", "bfs_block_td_noalloc"]
+            "bfs_block_td", "bfs_block_bu", "bfs_block_td_noalloc", "bfs_block_set_union"]
 
 
 class BfsError(RuntimeError):
@@ -45,24 +45,27 @@ class bfs_opts(ctypes.Structure):
                 ("beta", ctypes.c_double), ("timing", ctypes.c_int32), ("bu_serial", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("td_claim", ctypes.c_int32), ("small_edges", ctypes.c_int32),
                 ("persist_edges", ctypes.c_int32), ("persist_groups", ctypes.c_int32),
-                ("bu_head", ctypes.c_int32), ("td_prepass", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("bu_head", ctypes.c_int32), ("td_prepass", ctypes.c_int32), ("bu_segments", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class bfs_stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("td_levels", ctypes.c_int32), ("bu_levels", ctypes.c_int32),
-                ("pad0", ctypes.c_int32), ("reached", ctypes.c_int64), ("isolated", ctypes.c_int64),
+                ("fill_level", ctypes.c_int32), ("reached", ctypes.c_int64), ("isolated", ctypes.c_int64),
                 ("edges_examined", ctypes.c_int64),
                 ("total_ms", ctypes.c_double), ("launches", ctypes.c_int64 * 8), ("kernel_ms", ctypes.c_double * 8),
                 ("level_dir", ctypes.c_int8 * STATS_MAX_LEVELS), ("level_nf", ctypes.c_int64 * STATS_MAX_LEVELS),
                 ("level_mf", ctypes.c_int64 * STATS_MAX_LEVELS), ("level_mu", ctypes.c_int64 * STATS_MAX_LEVELS),
                 ("level_unvisited", ctypes.c_int64 * STATS_MAX_LEVELS),
                 ("level_examined", ctypes.c_int64 * STATS_MAX_LEVELS),
-                ("level_ms", ctypes.c_float * STATS_MAX_LEVELS)]
+                ("level_ms", ctypes.c_float * STATS_MAX_LEVELS), ("td_claims", ctypes.c_int64),
+                ("td_duplicates", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         L = min(self.levels, STATS_MAX_LEVELS)
         return {
             "levels": self.levels, "td_levels": self.td_levels, "bu_levels": self.bu_levels,
+            "fill_level": self.fill_level,
             "reached": self.reached, "isolated": self.isolated, "edges_examined": self.edges_examined, "total_ms": self.total_ms,
             "launches": {k: self.launches[i] for i, k in enumerate(KERNEL_KINDS)},
             "kernel_ms": {k: self.kernel_ms[i] for i, k in enumerate(KERNEL_KINDS)},
@@ -70,6 +73,7 @@ class bfs_stats(ctypes.Structure):
             "level_mf": list(self.level_mf[:L]), "level_mu": list(self.level_mu[:L]),
             "level_unvisited": list(self.level_unvisited[:L]), "level_examined": list(self.level_examined[:L]),
             "level_ms": list(self.level_ms[:L]),
+            "td_claims": self.td_claims, "td_duplicates": self.td_duplicates,
         }
 
 
@@ -107,8 +111,9 @@ def lib():
         L.bfs_block_bu.argtypes = [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int64, _vp, _vp, _vp, _vp,
                                    ctypes.c_size_t, _vp]
         L.bfs_block_td_noalloc.argtypes = [_vp, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
+        L.bfs_block_set_union.argtypes = [_vp, ctypes.c_int]
         for name in ("bfs_create_graph_csr", "bfs_create_graph_dcsc", "bfs_run", "bfs_run_multi", "bfs_block_td",
-                     "bfs_block_bu", "bfs_block_td_noalloc"):
+                     "bfs_block_bu", "bfs_block_td_noalloc", "bfs_block_set_union"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -264,6 +269,11 @@ def bfs_block_td(g: Graph, frontier: torch.Tensor, out_rows: torch.Tensor, out_p
                               _dev(out_parents, torch.int32, "out_parents", g.nrows),
                               _dev(nout, torch.int64, "nout", 1), _dev(ws, torch.uint8, "workspace"), ws.numel(),
                               _stream(stream)), "bfs_block_td")
+
+
+def bfs_block_set_union(g: Graph, mode: int):
+    """Union of the frontier columns in bfs_block_td: 0 by density, 1 sorted union when it fits, -1 accumulator."""
+    _check(lib().bfs_block_set_union(g.handle, int(mode)), "bfs_block_set_union")
 
 
 def bfs_block_td_noalloc(g: Graph, frontier: torch.Tensor, out_rows: torch.Tensor, out_parents: torch.Tensor,

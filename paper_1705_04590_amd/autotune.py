@@ -5,7 +5,8 @@ direction-invariant; the GPU tests check both):
   alpha, beta   the Section 4.4 switch thresholds
   bu_serial     entries a lane scans alone before its wave helps (bottom-up)
   grid_blocks   workgroup cap of the grid-stride kernels
-  td_claim      top-down claim: fetch-or on the visited bitmap or CAS on parent
+  td_claim      top-down claim: fetch-or on the visited bitmap, CAS on parent, or the
+                benign race (no atomic test, duplicates possible)
   small_edges   persistent top-down engine on (0, default caps) or off (-1)
   bu_head       bottom-up probes for ANY parents: automatic (0), row order (1),
                 three highest-degree neighbours (2), two hub-ranked neighbours (3)
@@ -31,7 +32,7 @@ ALPHAS = (15.0, 4.0, 8.0, 25.0, 40.0, 80.0, 160.0)
 BETAS = (18.0, 6.0, 36.0, 72.0)
 SERIALS = (16, 4, 8, 32)
 GRIDS = (2048, 1024, 4096)
-CLAIMS = (0, 1)
+CLAIMS = (0, 1, 2)
 ENGINE = (0, -1)
 HEADS = (0, 1, 2, 3)
 PREPASS = (0, -1)

@@ -62,6 +62,7 @@ struct bfs_graph {
     int64_t nrows = 0, ncols = 0, row_base = 0, col_base = 0, nzc = 0, nzr = 0;
     const int32_t *jc = nullptr, *ir = nullptr, *jr = nullptr, *ic = nullptr;
     const int64_t *cp = nullptr, *rp = nullptr;
+    int block_union = 0;   // bfs_block_set_union
     // derived metadata (device, library-owned, symmetric graphs only): bitmap
     // of vertices without entries, ids >= n in the last word set; their count
     uint64_t* d_iso = nullptr;
@@ -77,8 +78,9 @@ struct bfs_graph {
     int nhub = 0;
     bool hub_auto = false;   // frontier bitmap larger than the L2: ranked probes by default
     uint32_t* d_nbase = nullptr;   // per word: vertices with edges before it (head record index base)
-    // workgroups of the persistent top-down engine that fit on the device
+    // workgroups of the persistent top-down engines that fit on the device
     int persist_groups_max = 1;
+    int ms_groups_max = 1;
     // host metadata
     uint64_t* h_buf = nullptr;              // pinned: create-time readback only
 };
@@ -227,6 +229,7 @@ BlockWs block_ws(const bfs_graph* g, char* ws) {
     W.qlen = W.header;
     W.total = (int64_t*)(W.header + 1);
     W.range = W.header + 2;
+    W.skip = W.header + 5;
     W.q = (int32_t*)(ws + Lo.q);
     W.scan = (int64_t*)(ws + Lo.scan);
     W.tiles = (int32_t*)(ws + Lo.tiles);
@@ -245,11 +248,13 @@ BlockArgs block_args(const bfs_graph* g) {
     B.nzc = g->nzc; B.nzr = g->nzr; B.nnz = g->nnz;
     B.jc = g->jc; B.ir = g->ir; B.jr = g->jr; B.ic = g->ic; B.cp = g->cp; B.rp = g->rp;
     B.sorted = (g->flags & BFS_GRAPH_SORTED) != 0;
+    B.sort_union = g->block_union;
     return B;
 }
 
 struct MultiLayout {
-    size_t counters, src, visited, F, N, hubmark, qa, qb, scan, tiles, partial, par, lvl, total;
+    size_t counters, pctl, pctr, mstate, ctl_end, mrec, src, visited, F, N, hubmark, qa, qb, scan, tiles, partial,
+        par, lvl, total;
 };
 
 MultiLayout multi_layout(const bfs_graph* g) {
@@ -257,6 +262,12 @@ MultiLayout multi_layout(const bfs_graph* g) {
     const int64_t n = g->n;
     size_t o = 0;
     L.counters = o; o = align_up(o + sizeof(uint64_t) * SLOTS * SLOT_WORDS);
+    // the persistent engine's control block (cleared before each launch) and level records
+    L.pctl = o; o = align_up(o + sizeof(PersistCtl));
+    L.pctr = o; o = align_up(o + sizeof(uint64_t) * SLOTS * SLOT_WORDS);
+    L.mstate = o; o = align_up(o + sizeof(MsState));
+    L.ctl_end = o;
+    L.mrec = o; o = align_up(o + sizeof(int64_t) * 5 * BFS_STATS_MAX_LEVELS);
     L.src = o; o = align_up(o + sizeof(int64_t) * 64);
     L.visited = o; o = align_up(o + sizeof(uint64_t) * (size_t)n);
     L.F = o; o = align_up(o + sizeof(uint64_t) * (size_t)n);
@@ -349,7 +360,11 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     int64_t* scan = (int64_t*)(ws + Lo.scan);
     int32_t* tiles = (int32_t*)(ws + Lo.tiles);
     int64_t* partial = (int64_t*)(ws + Lo.partial);
-    const int claim_mode = o.parent_mode == BFS_PARENT_MIN ? CLAIM_MIN : (o.td_claim == 1 ? CLAIM_CAS : CLAIM_BITMAP);
+    const int claim_mode = o.parent_mode == BFS_PARENT_MIN ? CLAIM_MIN
+                           : o.td_claim == 1             ? CLAIM_CAS
+                           : o.td_claim == 2             ? CLAIM_BENIGN
+                                                         : CLAIM_BITMAP;
+    const bool any_bitmap = claim_mode == CLAIM_BITMAP || claim_mode == CLAIM_BENIGN;
     const int serial = o.bu_serial > 0 ? o.bu_serial : 16;
     Launch L{stream, o.grid_blocks > 0 ? o.grid_blocks : 2048};
     HostCtx* ctx = nullptr;
@@ -371,8 +386,9 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     // fill moves into the first bottom-up sweep (whole lines, once), or to a
     // fill pass at the end when no bottom-up level runs; the other claim
     // modes compare against -1 and need it before the first top-down level
-    const bool lazy_out = claim_mode == CLAIM_BITMAP && o.dir != BFS_DIR_TD && g->d_iso != nullptr;
+    const bool lazy_out = any_bitmap && o.dir != BFS_DIR_TD && g->d_iso != nullptr;
     bool out_filled = !lazy_out;
+    int32_t fill_level = -1;   // reported in stats: who wrote the -1 of the vertices not reached
     HIP_TRY(T.begin(BFS_K_INIT));
     launch_init(L, parent, depth, n, visited, vprev, fbits, claim, g->d_iso, W, qcur, src, counters,
                 (int64_t)((Lo.ctl_end - Lo.counters) / sizeof(uint64_t)), !lazy_out);
@@ -440,7 +456,8 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             // forced top-down never switches: with alpha = 0 the rule m_f * alpha > m_u cannot fire
             const double eng_alpha = o.dir == BFS_DIR_TD ? 0.0 : o.alpha;
             HIP_TRY(T.begin(BFS_K_TD_EXPAND));
-            launch_td_persist<OffT>(L, claim_mode, groups, off, g->cols, parent, depth, visited, vprev, claim, qcur,
+            // the engine's small levels keep exact claims in the benign mode
+            launch_td_persist<OffT>(L, claim_mode == CLAIM_BENIGN ? CLAIM_BITMAP : claim_mode, groups, off, g->cols, parent, depth, visited, vprev, claim, qcur,
                                     qnext, n, in, d_small, (uint64_t*)(ws + Lo.pctr), (PersistCtl*)(ws + Lo.pctl),
                                     d_rec, rec_cap, eng_alpha, multi ? cap_multi : cap_one, multi ? cap_one / 2 : 0,
                                     (int64_t)1 << 40, scan, tiles, (int64_t*)(ws + Lo.pcsum));
@@ -524,7 +541,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                 // on-chip copy of the hubs' frontier bits; those it finds are
                 // visited before the edge pass, whose probes then skip them,
                 // which saves most of its claim atomics
-                prepass = claim_mode == CLAIM_BITMAP && o.dir == BFS_DIR_DO && g->nhub > 0 && prepass_edges >= 0 &&
+                prepass = any_bitmap && o.dir == BFS_DIR_DO && g->nhub > 0 && prepass_edges >= 0 &&
                           m_f >= prepass_edges;
                 if (prepass) {
                     HIP_TRY(T.begin(BFS_K_CONVERT));
@@ -541,6 +558,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                     launch_bu_sweep<OffT>(L, g->d_hubr, 3, g->d_iso, g->d_nbase, off, g->cols, fbits, hb, nbits,
                                           visited, vprev, parent, depth, W, next_depth, serial, slot, zslot,
                                           !out_filled, n, src);
+                    if (!out_filled) fill_level = level;
                     out_filled = true;
                     HIP_TRY(hipGetLastError());
                     HIP_TRY(T.end(BFS_K_TD_EXPAND, level));
@@ -557,7 +575,8 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                 HIP_TRY(T.end(BFS_K_TD_EXPAND, level));
                 HIP_TRY(T.begin(BFS_K_CONVERT));
                 fbits_stale = false;
-                launch_merge(L, claim_mode == CLAIM_MIN, visited, vprev, claim, fbits, W);
+                if (claim_mode == CLAIM_BENIGN) launch_merge_exact<OffT>(L, off, visited, vprev, fbits, W, slot);
+                else launch_merge(L, claim_mode == CLAIM_MIN, visited, vprev, claim, fbits, W);
                 HIP_TRY(hipGetLastError());
                 HIP_TRY(T.end(BFS_K_CONVERT, level));
                 if (st) {
@@ -596,21 +615,48 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                 HIP_TRY(T.end(BFS_K_CONVERT, level));
                 if (st) st->launches[BFS_K_CONVERT] += 1;
             }
+            // column-blocked level: the sweep leaves the row scans to one
+            // sub-step per column segment, in ascending order; the pending
+            // lists live in the queue and scan areas, unused by a
+            // bottom-up level
+            const int segs = o.bu_segments;
+            uint64_t* pend_a = segs ? (uint64_t*)(ws + Lo.q0) : nullptr;
+            uint64_t* pend_b = (uint64_t*)(ws + Lo.scan);
             HIP_TRY(T.begin(BFS_K_BU_SWEEP));
             launch_bu_sweep<OffT>(L, hk == 2 ? g->d_hubr : hk == 1 ? g->d_hub : g->d_head, hk, g->d_iso, g->d_nbase,
                                   off, g->cols, fbits, hb, nbits, visited, vprev, parent, depth, W, next_depth, serial,
-                                  slot, zslot, !out_filled, n, src);
+                                  slot, zslot, !out_filled, n, src, pend_a);
+            if (!out_filled) fill_level = level;
             out_filled = true;
+            const int64_t segw = segs ? (W + segs - 1) / segs : 0;
+            for (int sg = 0; sg < segs; ++sg) {
+                const int64_t seg_end = sg == segs - 1 ? n : std::min<int64_t>(n, (sg + 1) * segw * 64);
+                launch_bu_segment<OffT>(L, off, g->cols, fbits, sg % 2 ? pend_b : pend_a, slot + S_PEND0 + sg,
+                                        sg % 2 ? pend_a : pend_b, slot + S_PEND0 + sg + 1, seg_end, parent, depth,
+                                        nbits, visited, vprev, next_depth, serial, slot);
+            }
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_BU_SWEEP, level));
-            if (st) st->launches[BFS_K_BU_SWEEP] += 1;
+            if (st) st->launches[BFS_K_BU_SWEEP] += 1 + segs;
         }
         {
             bfs_status rs = readback(ctx, stream, slot, SLOT_WORDS, &h);
             if (rs != BFS_OK) return rs;
         }
-        const int64_t n_next = (int64_t)slot_sum(h, S_NNEXT);
-        const int64_t m_next = (int64_t)slot_sum(h, S_MNEXT);
+        int64_t n_next = (int64_t)slot_sum(h, S_NNEXT);
+        int64_t m_next = (int64_t)slot_sum(h, S_MNEXT);
+        const bool benign_td = claim_mode == CLAIM_BENIGN && cur_dir == 0 && m_f > 0;
+        if (benign_td) {
+            // the expansion counted every copy a thread took; the merge
+            // counted the new vertices and their edges once
+            const int64_t distinct = (int64_t)slot_sum(h, S_DISTINCT);
+            if (st) {
+                st->td_claims += n_next;
+                st->td_duplicates += n_next - distinct;
+            }
+            n_next = distinct;
+            m_next = (int64_t)slot_sum(h, S_MDISTINCT);
+        }
         const int64_t lvl_examined = cur_dir == 0 ? m_f : (int64_t)slot_sum(h, S_EXAMINED);
         examined += lvl_examined;
         if (st && level < BFS_STATS_MAX_LEVELS) {
@@ -632,9 +678,9 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
         n_f = n_next;
         m_f = m_next;
         prev_bu = cur_dir == 1;
-        if (prepass) {
+        if (prepass || benign_td) {
             // the next frontier is the merge's bitmap (the queue holds only
-            // the edge pass's winners)
+            // the edge pass's winners, or nothing after a benign-race level)
             fmt_queue = false;
             qlen_dev = nullptr;
         } else if (cur_dir == 0) {
@@ -647,6 +693,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
         if (level > n + 1) return fail(BFS_E_HIP, "level loop did not terminate");
     }
     if (!out_filled) {
+        fill_level = -2;
         HIP_TRY(T.begin(BFS_K_INIT));
         launch_fill_unreached(L, parent, depth, n, visited, g->d_iso, src);
         HIP_TRY(hipGetLastError());
@@ -655,6 +702,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     }
     if (st) {
         st->levels = level;
+        st->fill_level = fill_level;
         st->reached = reached;
         st->isolated = g->isolated;
         st->edges_examined = examined;
@@ -722,6 +770,13 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
     int64_t nd_len = 0;
     int level = 0;
     int64_t examined = 0, reached_pairs = 0;
+    // persistent engine for runs of small top-down levels (the same knobs as
+    // the single-source engine: small_edges < 0 switches it off)
+    bool engine_on = o.small_edges >= 0;
+    const int64_t eng_cap = o.persist_edges > 0 ? o.persist_edges : 65536;
+    int eng_groups = o.persist_groups > 0 ? o.persist_groups : 64;
+    eng_groups = std::max(1, std::min(eng_groups, g->ms_groups_max));
+    bool skip_engine = false;
     for (;;) {
         if (level >= 65535) return fail(BFS_E_UNSUPPORTED, "more than 65535 levels");
         if (o.dir == BFS_DIR_TD) cur_dir = 0;
@@ -732,6 +787,78 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
         uint64_t* zslot = counters + (size_t)((level + 1) % SLOTS) * SLOT_WORDS;
         uint64_t* pslot = counters + (size_t)((level + SLOTS - 1) % SLOTS) * SLOT_WORDS;
         const uint16_t next_level = (uint16_t)(level + 1);
+        if (cur_dir == 0 && engine_on && !skip_engine && m_f > 0 && m_f <= eng_cap) {
+            // the engine needs the frontier as a queue and N clean
+            HIP_TRY(T.begin(BFS_K_CONVERT));
+            if (!fq_valid) {
+                launch_ms_mask_to_queue(L, F, n, qa, slot + M_SLOT_CONV);
+                fq_valid = true;
+                qlen = n_f;
+            }
+            if (n_dirty == 2) launch_clear_words(L, N, n);
+            else if (n_dirty == 1 && nd_len > 0) launch_ms_clear_queue(L, qb, nullptr, nd_len, N);
+            n_dirty = 0;
+            launch_clear_words(L, (uint64_t*)(ws + Lo.pctl), (int64_t)((Lo.ctl_end - Lo.pctl) / sizeof(uint64_t)));
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(T.end(BFS_K_CONVERT, level));
+            const int rec_cap = (st && level < BFS_STATS_MAX_LEVELS) ? BFS_STATS_MAX_LEVELS - level : 0;
+            const double eng_alpha = o.dir == BFS_DIR_TD ? 0.0 : o.alpha;
+            HIP_TRY(T.begin(BFS_K_MS_LEVEL));
+            launch_ms_persist<OffT>(L, eng_groups, off, g->cols, n, full, F, N, visited, qa, qb, par_vm, lvl_vm,
+                                    hubmark, serial, MsIn{qlen, n_f, m_f, m_u, level}, (MsState*)(ws + Lo.mstate),
+                                    (uint64_t*)(ws + Lo.pctr), (PersistCtl*)(ws + Lo.pctl), (int64_t*)(ws + Lo.mrec),
+                                    rec_cap, eng_alpha, eng_cap, 65535 - level, counters);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(T.end(BFS_K_MS_LEVEL, -1));
+            const uint64_t* hb = nullptr;
+            {
+                // the state, then (after its alignment) the level records, in one copy
+                const int nw = (int)((Lo.mrec - Lo.mstate) / sizeof(uint64_t)) + 5 * rec_cap;
+                bfs_status rs = readback(ctx, stream, ws + Lo.mstate, nw, &hb);
+                if (rs != BFS_OK) return rs;
+            }
+            MsState es;
+            std::memcpy(&es, hb, sizeof(es));
+            const int64_t* recs = (const int64_t*)((const char*)hb + (Lo.mrec - Lo.mstate));
+            if (st) st->launches[BFS_K_MS_LEVEL] += 1;
+            if (es.reason == ENG_NOT_RUN) {
+                // the workgroups could not all be resident at once: nothing
+                // was touched, this level goes through the per-level kernels
+                engine_on = false;
+                continue;
+            }
+            if (es.reason == ENG_TIMEOUT) return fail(BFS_E_HIP, "multi-source engine: grid barrier timed out");
+            if (st) {
+                for (int64_t i = 0; i < es.levels_done && i < rec_cap; ++i) {
+                    const int lv = level + (int)i;
+                    const int64_t* r = recs + i * 5;
+                    st->level_dir[lv] = 0;
+                    st->level_nf[lv] = r[0];
+                    st->level_mf[lv] = r[1];
+                    st->level_mu[lv] = r[2];
+                    st->level_unvisited[lv] = -1;
+                    st->level_examined[lv] = r[4];
+                }
+                st->td_levels += (int32_t)es.levels_done;
+            }
+            if (es.swapped) {
+                uint64_t* t = F; F = N; N = t;
+                int32_t* tq = qa; qa = qb; qb = tq;
+            }
+            level += (int)es.levels_done;
+            examined += es.examined;
+            reached_pairs += es.reached;
+            qlen = es.qlen;
+            n_f = es.n_f;
+            m_f = es.m_f;
+            m_u = es.m_u;
+            fq_valid = true;
+            if (es.reason == ENG_EMPTY) break;
+            // a cap hit at entry: this level through the per-level kernels
+            skip_engine = es.levels_done == 0;
+            continue;
+        }
+        skip_engine = false;
         if (cur_dir == 0) {
             HIP_TRY(T.begin(BFS_K_CONVERT));
             int conv = 0;
@@ -809,6 +936,7 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
     if (st) {
         st->launches[BFS_K_MS_OUTPUT] += 1;
         st->levels = level;
+        st->fill_level = -1;
         st->reached = reached_pairs;
         st->isolated = g->isolated;
         st->edges_examined = examined;
@@ -996,6 +1124,7 @@ bfs_status bfs_create_graph_csr(int64_t n, const void* d_offsets, int offset_byt
         }
     }
     g->persist_groups_max = g->off_bytes == 4 ? persist_max_groups<int32_t>() : persist_max_groups<int64_t>();
+    g->ms_groups_max = g->off_bytes == 4 ? ms_persist_max_groups<int32_t>() : ms_persist_max_groups<int64_t>();
     {
         // hub-ranked probes pay off only when the frontier bitmap does not fit in L2
         int l2 = 0;
@@ -1111,7 +1240,9 @@ bfs_status bfs_run(bfs_graph* g, int64_t source, const bfs_opts* opts, int32_t* 
     if (o.dir < BFS_DIR_DO || o.dir > BFS_DIR_BU) return fail(BFS_E_INVALID_ARG, "bad dir %d", o.dir);
     if (o.parent_mode != BFS_PARENT_ANY && o.parent_mode != BFS_PARENT_MIN)
         return fail(BFS_E_INVALID_ARG, "bad parent_mode %d", o.parent_mode);
-    if (o.td_claim != 0 && o.td_claim != 1) return fail(BFS_E_INVALID_ARG, "bad td_claim %d", o.td_claim);
+    if (o.td_claim < 0 || o.td_claim > 2) return fail(BFS_E_INVALID_ARG, "bad td_claim %d", o.td_claim);
+    if (o.bu_segments < 0 || o.bu_segments > BU_MAX_SEGMENTS)
+        return fail(BFS_E_INVALID_ARG, "bu_segments %d outside [0, %d]", o.bu_segments, BU_MAX_SEGMENTS);
     if (!(o.alpha > 0) || !(o.beta > 0)) return fail(BFS_E_INVALID_ARG, "alpha and beta must be > 0");
     if (source < 0 || source >= g->n)
         return fail(BFS_E_OUT_OF_RANGE, "source %lld outside [0, %lld)", (long long)source, (long long)g->n);
@@ -1235,6 +1366,13 @@ bfs_status bfs_block_td_noalloc(bfs_graph* g, const int32_t* d_frontier, int64_t
     HIP_TRY(hipGetLastError());
     D.last = Lo;
     D.zeroed = true;
+    return BFS_OK;
+}
+
+bfs_status bfs_block_set_union(bfs_graph* g, int mode) {
+    if (!g || g->kind != KIND_DCSC) return fail(BFS_E_INVALID_ARG, "graph handle is not a DCSC block");
+    if (mode < -1 || mode > 1) return fail(BFS_E_INVALID_ARG, "union mode %d outside [-1, 1]", mode);
+    g->block_union = mode;
     return BFS_OK;
 }
 

@@ -70,10 +70,11 @@ __global__ __launch_bounds__(TD_BLOCK) void k_blk_expand(
     const int64_t* __restrict__ cp, const int32_t* __restrict__ jc, const int32_t* __restrict__ ir,
     const int32_t* __restrict__ q, const uint64_t* __restrict__ qlen_dev, const int64_t* __restrict__ scan,
     const int32_t* __restrict__ tile_start, const int64_t* __restrict__ total_dev, int64_t nnz, int64_t nrows,
-    int64_t col_base, uint32_t* __restrict__ spa, uint64_t* __restrict__ occ) {
+    int64_t col_base, uint32_t* __restrict__ spa, uint64_t* __restrict__ occ, const uint64_t* __restrict__ skip) {
     __shared__ int32_t s_start[TD_TILE + 1];
     __shared__ int64_t s_base[TD_TILE + 1];
     __shared__ uint32_t s_par[TD_TILE + 1];
+    if (*skip) return;   // the sorted union already wrote the output
     const int64_t qlen = (int64_t)*qlen_dev;
     const int64_t total = *total_dev;
     const int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
@@ -132,6 +133,13 @@ struct WordPopc {
     __device__ int64_t operator()(int64_t i) const { return __popcll(w[i]); }
 };
 
+// occupied words of the accumulator; none when the sorted union ran instead
+struct OccPopc {
+    const uint64_t* w;
+    const uint64_t* skip;
+    __device__ int64_t operator()(int64_t i) const { return *skip ? 0 : __popcll(w[i]); }
+};
+
 // emits the rows of occupied word i in ascending order and clears what it read
 struct SpaEmit {
     uint64_t* occ;
@@ -139,6 +147,7 @@ struct SpaEmit {
     int32_t* out_rows;
     int32_t* out_parents;
     int64_t* nout;
+    const uint64_t* skip;
     __device__ void item(int64_t i, int64_t before, int64_t d) const {
         if (!d) return;
         uint64_t x = occ[i];
@@ -154,8 +163,93 @@ struct SpaEmit {
         }
         occ[i] = 0;
     }
-    __device__ void last(int64_t, int64_t total) const { *nout = total; }
+    __device__ void last(int64_t, int64_t total) const {
+        if (!*skip) *nout = total;
+    }
 };
+
+// ---------------------------------------------------------------- sorted union
+// Hypersparse frontiers (Section 5.2 weighs a sparse accumulator against a
+// heap-based union of the frontier columns; for very few columns the
+// accumulator's ordered pass over all nrows/64 occupied words dominates).
+// One workgroup gathers the entries (r, col_base + k) of the frontier
+// columns into LDS as 64-bit keys r << 32 | parent, sorts them (bitonic),
+// and keeps the first key of every row: rows come out ascending, each with
+// its smallest parent, the same pairs the accumulator gives.  When the
+// columns hold more than SORT_CAP entries it writes nothing and leaves
+// `skip` at 0, and the accumulator path that follows does the work.
+constexpr int SORT_CAP = 8192;
+constexpr int SORT_BLOCK = 1024;
+
+__global__ __launch_bounds__(SORT_BLOCK) void k_blk_sorted_union(
+    const int64_t* __restrict__ cp, const int32_t* __restrict__ jc, const int32_t* __restrict__ ir,
+    const int32_t* __restrict__ q, const uint64_t* __restrict__ qlen_dev, const int64_t* __restrict__ scan,
+    const int64_t* __restrict__ total_dev, int64_t col_base, int32_t* __restrict__ out_rows,
+    int32_t* __restrict__ out_parents, int64_t* __restrict__ nout, uint64_t* __restrict__ skip) {
+    __shared__ uint64_t key[SORT_CAP];
+    __shared__ int32_t s_cnt[SORT_BLOCK];
+    const int tid = threadIdx.x;
+    const int64_t total = *total_dev;
+    const int64_t qlen = (int64_t)*qlen_dev;
+    if (total > SORT_CAP) return;   // skip stays 0: the accumulator runs
+    int np = 2;
+    while (np < total) np <<= 1;
+    for (int e = tid; e < np; e += SORT_BLOCK) {
+        uint64_t k = ~0ull;
+        if (e < total) {
+            // the queue entry owning edge e: last i with scan[i] <= e
+            int64_t lo = 0, hi = qlen - 1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (scan[mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            const int32_t h = q[lo];
+            const int32_t r = ir[cp[h] + (e - scan[lo])];
+            k = ((uint64_t)(uint32_t)r << 32) | (uint32_t)(col_base + jc[h]);
+        }
+        key[e] = k;
+    }
+    __syncthreads();
+    for (int size = 2; size <= np; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = tid; t < np / 2; t += SORT_BLOCK) {
+                const int i = 2 * t - (t & (stride - 1));   // lower index of the pair
+                const int j = i + stride;
+                const bool up = (i & size) == 0;
+                const uint64_t a = key[i], b = key[j];
+                if ((a > b) == up) { key[i] = b; key[j] = a; }
+            }
+            __syncthreads();
+        }
+    }
+    // first key of every row, compacted in order: each thread takes a run of
+    // consecutive keys, counts its row starts, and a block prefix places them
+    const int per = (np + SORT_BLOCK - 1) / SORT_BLOCK;
+    const int a0 = tid * per, a1 = min(a0 + per, (int)total);
+    int c = 0;
+    for (int i = a0; i < a1; ++i)
+        if (i == 0 || (key[i] >> 32) != (key[i - 1] >> 32)) ++c;
+    s_cnt[tid] = c;
+    __syncthreads();
+    for (int d = 1; d < SORT_BLOCK; d <<= 1) {
+        const int x = tid >= d ? s_cnt[tid - d] : 0;
+        __syncthreads();
+        s_cnt[tid] += x;
+        __syncthreads();
+    }
+    int pos = s_cnt[tid] - c;
+    for (int i = a0; i < a1; ++i) {
+        if (i == 0 || (key[i] >> 32) != (key[i - 1] >> 32)) {
+            out_rows[pos] = (int32_t)(key[i] >> 32);
+            out_parents[pos] = (int32_t)(uint32_t)key[i];
+            ++pos;
+        }
+    }
+    if (tid == SORT_BLOCK - 1) {
+        *nout = s_cnt[SORT_BLOCK - 1];
+        *skip = 1;
+    }
+}
 
 // ---------------------------------------------------------------- bottom-up
 // range[0] = first JR index with row >= row_lo, range[1] = first with row >=
@@ -333,13 +427,22 @@ void launch_block_td(const Launch& L, const BlockArgs& B, const int32_t* F, int6
     const int64_t qmax = nf < B.nzc ? nf : B.nzc;
     launch_scan(L.stream, QueueDegree<int64_t>{B.cp, W.q}, W.qlen, qmax, W.partial,
                 TileSink{W.scan, W.tiles, W.total});
+    // hypersparse frontier: when the frontier's columns are expected to hold
+    // at most SORT_CAP entries (|F| times the mean column length), the sorted
+    // union takes the call, unless they hold more (then it leaves the skip
+    // word at 0 and the accumulator runs)
+    const bool sorted_union = B.sort_union >= 0 &&
+                              (B.sort_union == 1 || (double)nf * (double)B.nnz <= (double)SORT_CAP * (double)B.ncols);
+    if (sorted_union)
+        hipLaunchKernelGGL(k_blk_sorted_union, dim3(1), dim3(SORT_BLOCK), 0, L.stream, B.cp, B.jc, B.ir, W.q, W.qlen,
+                           W.scan, W.total, B.col_base, out_rows, out_parents, nout, W.skip);
     const int64_t tiles_max = (B.nnz + TD_TILE - 1) / TD_TILE;
     hipLaunchKernelGGL(k_blk_expand, dim3(grid_for(tiles_max, 1, L.grid_cap)), dim3(TD_BLOCK), 0, L.stream, B.cp,
                        B.jc, B.ir, W.q, W.qlen, W.scan, W.tiles, W.total, B.nnz, B.nrows, B.col_base, W.spa,
-                       W.occ);
+                       W.occ, W.skip);
     const int64_t wr = (B.nrows + 63) / 64;
-    launch_scan(L.stream, WordPopc{W.occ}, (const uint64_t*)nullptr, wr, W.partial,
-                SpaEmit{W.occ, W.spa, out_rows, out_parents, nout});
+    launch_scan(L.stream, OccPopc{W.occ, W.skip}, (const uint64_t*)nullptr, wr, W.partial,
+                SpaEmit{W.occ, W.spa, out_rows, out_parents, nout, W.skip});
 }
 
 void launch_block_bu(const Launch& L, const BlockArgs& B, const uint64_t* fbits, uint64_t* completed,

@@ -31,6 +31,7 @@
 namespace bfsk {
 
 constexpr int BU_WIN = 512;   // compacted-list window per wave (entries)
+constexpr int FILL_GW = BU_WIN / WAVE;   // words per group of a sweep that writes the fill
 
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -60,10 +61,21 @@ __device__ __forceinline__ uint64_t stream_load(const uint64_t* p) { return __bu
 // frontier bitmap in memory.
 //
 // FILL = 1 (first bottom-up level of a search whose outputs were left
-// uninitialised): after each group, the entries of its isolated and still
-// unreached vertices get -1, 64 consecutive entries per store, so together
-// with the hits every line of the outputs is written once on this level.
-template <typename OffT, int HUB, int FILL>
+// uninitialised): every output entry of the group's vertices that were not
+// visited before this level is written here, once: hits get their parent
+// and depth, isolated and still unreached vertices -1.  The hits are not
+// stored as they are found; each entry's result goes to its slot of the
+// compacted list in LDS (the slot of its head index, consumed one round
+// earlier), and after the group one pass per 64-vertex word writes the
+// word's entries with 64 consecutive stores, so each output line is written
+// by one instruction instead of once by the scattered hit stores and again
+// by a fill pass.  Groups are then at most FILL_GW words, so the whole group
+// fits one list window.
+// SEG = 1 (column-blocked sweep): the rows are not scanned past their head
+// here; a vertex that still needs its row is appended to the pending list
+// `pend` (vertex id, row position to resume at), and the sub-steps that
+// follow (k_bu_segment) scan those rows one column segment at a time.
+template <typename OffT, int HUB, int FILL, int SEG>
 __device__ __forceinline__ void bu_sweep_body(
     const int4* __restrict__ head, const uint64_t* __restrict__ iso, const uint32_t* __restrict__ nbase,
     const OffT* __restrict__ off, const int32_t* __restrict__ cols,
@@ -71,7 +83,7 @@ __device__ __forceinline__ void bu_sweep_body(
     uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev, int32_t* __restrict__ parent,
     int32_t* __restrict__ depth, int64_t W, int GW,
     int32_t next_depth, int serial_len, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot, int64_t n,
-    int64_t src) {
+    int64_t src, uint64_t* __restrict__ pend) {
     __shared__ int32_t s_list[BU_BLOCK / WAVE][BU_WIN];
     __shared__ int32_t s_hidx[BU_BLOCK / WAVE][BU_WIN];
     __shared__ unsigned long long s_nb[BU_BLOCK / WAVE][WAVE];
@@ -92,8 +104,10 @@ __device__ __forceinline__ void bu_sweep_body(
     int64_t w0 = 0;
     // v found its parent at row position pos
     auto found = [&](int32_t v, int32_t par, int32_t pos, int32_t deg) {
-        parent[v] = par;
-        depth[v] = next_depth;
+        if (!FILL) {
+            parent[v] = par;
+            depth[v] = next_depth;
+        }
         atomicOr(&nbw[(v >> 6) - w0], 1ull << (v & 63));
         my_n += 1;
         my_m += (uint64_t)deg;
@@ -161,6 +175,24 @@ __device__ __forceinline__ void bu_sweep_body(
                 constexpr int32_t skip = HUB ? 0 : 3, pbase = HUB ? nprobe : 0;
                 int64_t beg = 0;
                 int32_t rp = deg;   // next entry to scan; deg when nothing is left
+                if (SEG) {
+                    // the row goes to the pending list of the first sub-step
+                    const bool pnd = HUB != 3 && act && par < 0 && deg > nprobe;
+                    const uint64_t pm = __ballot(pnd);
+                    if (pm) {
+                        const int leader = __ffsll((unsigned long long)pm) - 1;
+                        uint64_t b = 0;
+                        if (lane == leader)
+                            b = atomicAdd((unsigned long long*)&slot[S_PEND0], (unsigned long long)__popcll(pm));
+                        b = __shfl(b, leader, WAVE);
+                        if (pnd) pend[b + __popcll(pm & lanemask_lt())] = (uint64_t)(uint32_t)v | ((uint64_t)skip << 32);
+                    }
+                    if (pnd) my_x += (uint64_t)(HUB ? nprobe : 3);   // the head; the sub-steps count the rest
+                    else if (par >= 0) found(v, par, pos, deg);
+                    else if (act) my_x += (uint64_t)(deg > nprobe ? pbase + deg : deg);
+                    if (FILL && act) hlist[r + lane] = par;
+                    continue;
+                }
                 if (HUB != 3 && par < 0 && deg > nprobe) {
                     beg = (int64_t)off[v];
                     const int32_t lim = deg - skip > serial_len ? skip + serial_len : deg;
@@ -214,6 +246,8 @@ __device__ __forceinline__ void bu_sweep_body(
                 }
                 if (par >= 0) found(v, par, pos, deg);
                 else if (act) my_x += (uint64_t)(deg > nprobe ? pbase + deg : deg);
+                // the entry's result replaces its head index (read one round ago)
+                if (FILL && act) hlist[r + lane] = par;
             }
             wave_lds_sync();
         }
@@ -232,18 +266,26 @@ __device__ __forceinline__ void bu_sweep_body(
             }
         }
         if (FILL) {
-            // isolated (not hasrow) or unvisited and not found now; ids >= n
-            // and the source excluded
-            uint64_t neg = 0;
-            if (mine) {
-                neg = ~hasrow | (~wv & ~nb);
-                if (w == W - 1 && (n & 63)) neg &= (1ull << (n & 63)) - 1ull;
-                if (w == (src >> 6)) neg &= ~(1ull << (src & 63));
-            }
+            // word j of the group, one entry per lane: vertices unvisited at
+            // the start of the level take their list slot's result (parent
+            // or -1); isolated vertices take -1; vertices visited earlier
+            // keep what their level wrote.  Ids >= n and the source excluded.
+            const int first = incl - cnt;   // list index of this lane's word's first unvisited vertex
             for (int j = 0; j < GW; ++j) {
-                const uint64_t m = __shfl(neg, j, WAVE);
-                if ((m >> lane) & 1ull) {
-                    const int64_t v = (w0 + j) * WAVE + lane;
+                const int64_t wj = w0 + j;
+                if (wj >= W) break;
+                const uint64_t unv = ~__shfl(wv, j, WAVE);
+                uint64_t iso_j = ~__shfl(hasrow, j, WAVE);
+                const int base = __shfl(first, j, WAVE);
+                if (wj == W - 1 && (n & 63)) iso_j &= (1ull << (n & 63)) - 1ull;
+                if (wj == (src >> 6)) iso_j &= ~(1ull << (src & 63));
+                const uint64_t bit = 1ull << lane;
+                const int64_t v = wj * WAVE + lane;
+                if (unv & bit) {
+                    const int32_t par = hlist[base + __popcll(unv & lanemask_lt())];
+                    parent[v] = par;
+                    depth[v] = par >= 0 ? next_depth : -1;
+                } else if (iso_j & bit) {
                     parent[v] = -1;
                     depth[v] = -1;
                 }
@@ -261,22 +303,159 @@ __device__ __forceinline__ void bu_sweep_body(
         const uint64_t* __restrict__ hb, uint64_t* __restrict__ nbits, uint64_t* __restrict__ visited,             \
         uint64_t* __restrict__ vprev, int32_t* __restrict__ parent, int32_t* __restrict__ depth, int64_t W, int GW, \
         int32_t next_depth, int serial_len, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot, int64_t n,  \
-        int64_t src
+        int64_t src, uint64_t* __restrict__ pend
 #define BFS_SWEEP_ARGS                                                                                            \
     head, iso, nbase, off, cols, fbits, hb, nbits, visited, vprev, parent, depth, W, GW, next_depth, serial_len,   \
-        slot, zslot, n, src
+        slot, zslot, n, src, pend
 
 // the bottom-up step
-template <typename OffT, int HUB, int FILL>
-__global__ __launch_bounds__(BU_BLOCK) void k_bu_sweep(BFS_SWEEP_PARAMS) {
-    bu_sweep_body<OffT, HUB, FILL>(BFS_SWEEP_ARGS);
+template <typename OffT, int HUB, int FILL, int SEG>
+__global__ __launch_bounds__(BU_BLOCK, 5) void k_bu_sweep(BFS_SWEEP_PARAMS) {
+    bu_sweep_body<OffT, HUB, FILL, SEG>(BFS_SWEEP_ARGS);
 }
 
 // the hub pre-pass of a heavy top-down level (a kernel of its own name, so
 // profiles keep it apart from the bottom-up step)
 template <typename OffT, int FILL>
 __global__ __launch_bounds__(BU_BLOCK) void k_td_hub_prepass(BFS_SWEEP_PARAMS) {
-    bu_sweep_body<OffT, 3, FILL>(BFS_SWEEP_ARGS);
+    bu_sweep_body<OffT, 3, FILL, 0>(BFS_SWEEP_ARGS);
+}
+
+// ------------------------------------------------------------ column segments
+// One sub-step of a column-blocked bottom-up level (Alg. 4's sub-steps with
+// the completed mask, inside one device): every pending row (vertex v, row
+// position p) is scanned from p over its entries below `seg_end` only, in
+// row order, probing the frontier bitmap's words of this segment (an
+// L2-sized slice when the segments are chosen so).  The first frontier entry
+// found is v's parent: the rows are sorted and the segments ascend, so it is
+// the first frontier entry of the whole row.  A row that reaches an entry
+// >= seg_end without a hit goes, with that position, to the pending list of
+// the next sub-step; the last sub-step has seg_end = n.  Found vertices set
+// their bits of nbits / visited / vprev with atomics (the words are shared
+// between waves here) and write their outputs.
+template <typename OffT>
+__global__ __launch_bounds__(BU_BLOCK) void k_bu_segment(
+    const OffT* __restrict__ off, const int32_t* __restrict__ cols, const uint64_t* __restrict__ fbits,
+    const uint64_t* __restrict__ pin, const uint64_t* __restrict__ cin, uint64_t* __restrict__ pout,
+    uint64_t* __restrict__ cout, int64_t seg_end, int32_t* __restrict__ parent, int32_t* __restrict__ depth,
+    uint64_t* __restrict__ nbits, uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev,
+    int32_t next_depth, int serial_len, uint64_t* __restrict__ slot) {
+    const int lane = lane_id();
+    const int64_t count = (int64_t)*cin;
+    const int64_t nwaves = (int64_t)gridDim.x * (BU_BLOCK / WAVE);
+    const int32_t lim_id = seg_end < 2147483647LL ? (int32_t)seg_end : 2147483647;
+    uint64_t my_n = 0, my_m = 0, my_x = 0;
+    const int64_t wi = (int64_t)blockIdx.x * (BU_BLOCK / WAVE) + threadIdx.x / WAVE;
+    for (int64_t i0 = wi * WAVE; i0 < count; i0 += nwaves * WAVE) {
+        const int64_t i = i0 + lane;
+        const bool act = i < count;
+        int32_t v = 0, rp = 0, deg = 0;
+        int64_t beg = 0;
+        if (act) {
+            const uint64_t e = pin[i];
+            v = (int32_t)(uint32_t)e;
+            rp = (int32_t)(e >> 32);
+            beg = (int64_t)off[v];
+            deg = (int32_t)((int64_t)off[v + 1] - beg);
+        }
+        const int32_t rp0 = rp;
+        int32_t par = -1;
+        bool stop = false;   // reached an entry of a later segment
+        const int32_t* row = cols + beg;
+        if (act) {
+            const int32_t lim = deg - rp > serial_len ? rp + serial_len : deg;
+            for (; rp < lim; rp += 4) {
+                const int32_t c0 = row[rp];
+                const int32_t c1 = rp + 1 < lim ? row[rp + 1] : lim_id;
+                const int32_t c2 = rp + 2 < lim ? row[rp + 2] : lim_id;
+                const int32_t c3 = rp + 3 < lim ? row[rp + 3] : lim_id;
+                const uint64_t f0 = c0 < lim_id ? fbits[c0 >> 6] : 0ull;
+                const uint64_t f1 = c1 < lim_id ? fbits[c1 >> 6] : 0ull;
+                const uint64_t f2 = c2 < lim_id ? fbits[c2 >> 6] : 0ull;
+                const uint64_t f3 = c3 < lim_id ? fbits[c3 >> 6] : 0ull;
+                if (c0 >= lim_id) { stop = true; break; }
+                if (bit_of(f0, c0)) { par = c0; break; }
+                if (rp + 1 >= lim) { rp += 1; break; }
+                if (c1 >= lim_id) { rp += 1; stop = true; break; }
+                if (bit_of(f1, c1)) { par = c1; rp += 1; break; }
+                if (rp + 2 >= lim) { rp += 2; break; }
+                if (c2 >= lim_id) { rp += 2; stop = true; break; }
+                if (bit_of(f2, c2)) { par = c2; rp += 2; break; }
+                if (rp + 3 >= lim) { rp += 3; break; }
+                if (c3 >= lim_id) { rp += 3; stop = true; break; }
+                if (bit_of(f3, c3)) { par = c3; rp += 3; break; }
+            }
+            if (rp > lim) rp = lim;
+        }
+        // rows still open after serial_len entries: the whole wave, 64 at a time
+        uint64_t rem = __ballot(act && par < 0 && !stop && rp < deg);
+        while (rem) {
+            const int l = __ffsll((unsigned long long)rem) - 1;
+            rem &= rem - 1;
+            const int32_t* lrow = cols + __shfl(beg, l, WAVE);
+            const int32_t pb = __shfl(rp, l, WAVE);
+            const int32_t pe = __shfl(deg, l, WAVE);
+            int32_t got = -1, at = pe;
+            bool out = false;
+            for (int32_t b = pb; b < pe; b += WAVE) {
+                const int32_t x = b + lane;
+                int32_t c = lim_id;
+                bool hit = false;
+                if (x < pe) {
+                    c = lrow[x];
+                    hit = c < lim_id && bit_of(fbits[c >> 6], c);
+                }
+                const uint64_t hm = __ballot(hit);
+                const uint64_t om = __ballot(x < pe && c >= lim_id);
+                if (hm | om) {
+                    const int fh = hm ? __ffsll((unsigned long long)hm) - 1 : WAVE;
+                    const int fo = om ? __ffsll((unsigned long long)om) - 1 : WAVE;
+                    if (fh < fo) {
+                        got = __shfl(c, fh, WAVE);
+                        at = b + fh;
+                    } else {
+                        out = true;
+                        at = b + fo;
+                    }
+                    break;
+                }
+            }
+            if (lane == l) {
+                par = got;
+                stop = out;
+                rp = at;
+            }
+        }
+        if (act) {
+            if (par >= 0) {
+                parent[v] = par;
+                depth[v] = next_depth;
+                const unsigned long long bit = 1ull << (v & 63);
+                __hip_atomic_fetch_or((unsigned long long*)&nbits[v >> 6], bit, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_or((unsigned long long*)&visited[v >> 6], bit, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_or((unsigned long long*)&vprev[v >> 6], bit, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+                my_n += 1;
+                my_m += (uint64_t)deg;
+                my_x += (uint64_t)(rp - rp0 + 1);
+            } else {
+                my_x += (uint64_t)(rp - rp0);   // up to the segment's end or the row's
+            }
+        }
+        const bool again = act && par < 0 && stop;
+        const uint64_t am = __ballot(again);
+        if (am) {
+            const int leader = __ffsll((unsigned long long)am) - 1;
+            uint64_t b = 0;
+            if (lane == leader) b = atomicAdd((unsigned long long*)cout, (unsigned long long)__popcll(am));
+            b = __shfl(b, leader, WAVE);
+            if (again) pout[b + __popcll(am & lanemask_lt())] = (uint64_t)(uint32_t)v | ((uint64_t)rp << 32);
+        }
+    }
+    uint64_t* ln = slot_line(slot);
+    block_add3<BU_BLOCK / WAVE>(my_n, my_m, my_x, &ln[S_NNEXT], &ln[S_MNEXT], &ln[S_EXAMINED]);
 }
 #undef BFS_SWEEP_PARAMS
 #undef BFS_SWEEP_ARGS
@@ -294,31 +473,45 @@ void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t*
                      const OffT* off, const int32_t* cols, const uint64_t* fbits, const uint64_t* hb, uint64_t* nbits,
                      uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W,
                      int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot, bool fill, int64_t n,
-                     int64_t src) {
-    const int gw = group_words(W, L.grid_cap * (BU_BLOCK / WAVE));
+                     int64_t src, uint64_t* pend) {
+    int gw = group_words(W, L.grid_cap * (BU_BLOCK / WAVE));
+    if (fill && gw > FILL_GW) gw = FILL_GW;
     const int64_t G = (W + gw - 1) / gw;
     const int g = grid_for(G, BU_BLOCK / WAVE, L.grid_cap);
-#define BFS_SWEEP(H, F)                                                                                          \
-    hipLaunchKernelGGL((k_bu_sweep<OffT, H, F>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off, cols, \
-                       fbits, hb, nbits, visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot, zslot, n, \
-                       src)
+#define BFS_SWEEP(H, F, S)                                                                                       \
+    hipLaunchKernelGGL((k_bu_sweep<OffT, H, F, S>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off,  \
+                       cols, fbits, hb, nbits, visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot,  \
+                       zslot, n, src, pend)
 #define BFS_PREPASS(F)                                                                                              \
     hipLaunchKernelGGL((k_td_hub_prepass<OffT, F>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off,    \
                        cols, fbits, hb, nbits, visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot,     \
-                       zslot, n, src)
-    if (fill) {
-        if (hub == 3) BFS_PREPASS(1);
-        else if (hub == 2) BFS_SWEEP(2, 1);
-        else if (hub == 1) BFS_SWEEP(1, 1);
-        else BFS_SWEEP(0, 1);
+                       zslot, n, src, pend)
+#define BFS_SWEEP_H(F, S)                 \
+    if (hub == 2) BFS_SWEEP(2, F, S);     \
+    else if (hub == 1) BFS_SWEEP(1, F, S); \
+    else BFS_SWEEP(0, F, S);
+    if (hub == 3) {
+        if (fill) BFS_PREPASS(1);
+        else BFS_PREPASS(0);
+    } else if (pend) {
+        if (fill) { BFS_SWEEP_H(1, 1) }
+        else { BFS_SWEEP_H(0, 1) }
     } else {
-        if (hub == 3) BFS_PREPASS(0);
-        else if (hub == 2) BFS_SWEEP(2, 0);
-        else if (hub == 1) BFS_SWEEP(1, 0);
-        else BFS_SWEEP(0, 0);
+        if (fill) { BFS_SWEEP_H(1, 0) }
+        else { BFS_SWEEP_H(0, 0) }
     }
+#undef BFS_SWEEP_H
 #undef BFS_SWEEP
 #undef BFS_PREPASS
+}
+
+template <typename OffT>
+void launch_bu_segment(const Launch& L, const OffT* off, const int32_t* cols, const uint64_t* fbits,
+                       const uint64_t* pin, const uint64_t* cin, uint64_t* pout, uint64_t* cout, int64_t seg_end,
+                       int32_t* parent, int32_t* depth, uint64_t* nbits, uint64_t* visited, uint64_t* vprev,
+                       int32_t next_depth, int serial_len, uint64_t* slot) {
+    hipLaunchKernelGGL(k_bu_segment<OffT>, dim3(L.grid_cap), dim3(BU_BLOCK), 0, L.stream, off, cols, fbits, pin, cin,
+                       pout, cout, seg_end, parent, depth, nbits, visited, vprev, next_depth, serial_len, slot);
 }
 
 // ------------------------------------------------------------------ row heads
@@ -524,7 +717,10 @@ void launch_hub_gather(const Launch& L, const uint64_t* fbits, const int32_t* hu
     template void launch_bu_sweep<T>(const Launch&, const int4*, int, const uint64_t*, const uint32_t*,          \
                                      const T*, const int32_t*, const uint64_t*, const uint64_t*, uint64_t*,      \
                                      uint64_t*, uint64_t*, int32_t*, int32_t*, int64_t, int32_t, int, uint64_t*, \
-                                     uint64_t*, bool, int64_t, int64_t);                                         \
+                                     uint64_t*, bool, int64_t, int64_t, uint64_t*);                              \
+    template void launch_bu_segment<T>(const Launch&, const T*, const int32_t*, const uint64_t*, const uint64_t*, \
+                                       const uint64_t*, uint64_t*, uint64_t*, int64_t, int32_t*, int32_t*,       \
+                                       uint64_t*, uint64_t*, uint64_t*, int32_t, int, uint64_t*);                \
     template void launch_deg_hist<T>(const Launch&, const T*, int64_t, uint32_t*, int);                          \
     template void launch_hub_ranks<T>(const Launch&, const T*, int64_t, int64_t, const int4*, int64_t,          \
                                       uint64_t*, uint32_t*, int64_t*, int32_t*, int4*);                         \

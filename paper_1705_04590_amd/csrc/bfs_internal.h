@@ -33,8 +33,12 @@ constexpr int BU_BLOCK = 256;                 // 4 waves, one 64-vertex word per
 // from each of thousands of workgroups serialises them.  Counters whose
 // running value matters on the device (the queue append position S_QLEN,
 // word 4 = queue length of a conversion) live in line 0 only.
-enum { S_QLEN = 0, S_NNEXT = 1, S_MNEXT = 2, S_EXAMINED = 3, SLOT_LINE = 16, SLOT_SPREAD = 16,
-       SLOT_WORDS = SLOT_LINE * SLOT_SPREAD, SLOTS = 3 };
+// S_PEND0 + s (line 0) = length of the pending list of a column-blocked
+// bottom-up level's sub-step s (at most BU_MAX_SEGMENTS sub-steps).
+enum { S_QLEN = 0, S_NNEXT = 1, S_MNEXT = 2, S_EXAMINED = 3, S_DISTINCT = 5, S_PEND0 = 6, S_MDISTINCT = 15,
+       SLOT_LINE = 16, SLOT_SPREAD = 16, SLOT_WORDS = SLOT_LINE * SLOT_SPREAD, SLOTS = 3 };
+constexpr int BU_MAX_SEGMENTS = 8;
+static_assert(S_PEND0 + BU_MAX_SEGMENTS < S_MDISTINCT, "pending counts must fit line 0 of a slot");
 
 // sum of word `w` over the lines of a slot copied to the host
 inline uint64_t slot_sum(const uint64_t* h, int w) {
@@ -51,8 +55,11 @@ struct Launch {
     int grid_cap;   // workgroup cap for grid-stride kernels
 };
 
-// Top-down claim modes.
-enum { CLAIM_BITMAP = 0, CLAIM_CAS = 1, CLAIM_MIN = 2 };
+// Top-down claim modes.  BENIGN takes a child with no atomic test: every
+// thread that saw it unvisited writes its parent (several may, any of them is
+// valid) and sets its visited bit with an atomic whose result is unused; the
+// level queues nothing, its next frontier is the merge's exact bitmap.
+enum { CLAIM_BITMAP = 0, CLAIM_CAS = 1, CLAIM_MIN = 2, CLAIM_BENIGN = 3 };
 
 // ---- single source -------------------------------------------------------
 template <typename OffT>
@@ -87,12 +94,21 @@ void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t*
 // only, as a pre-pass of a top-down level (visited updated, nbits/vprev not).  fill: the outputs
 // were not initialised; the sweep also writes -1 to every entry of the
 // unreached and isolated vertices (the source, of id src, excepted)
+// pend (may be NULL): column-blocked level; rows that need scanning past
+// their head are appended to pend (count in slot[S_PEND0]) for the sub-steps
 template <typename OffT>
 void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t* iso, const uint32_t* nbase,
                      const OffT* off, const int32_t* cols, const uint64_t* fbits, const uint64_t* hb, uint64_t* nbits,
                      uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W,
                      int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot, bool fill, int64_t n,
-                     int64_t src);
+                     int64_t src, uint64_t* pend = nullptr);
+// one column-segment sub-step: pending rows (count *cin) scanned over their
+// entries < seg_end; rows that reach a later segment go to pout (count *cout)
+template <typename OffT>
+void launch_bu_segment(const Launch& L, const OffT* off, const int32_t* cols, const uint64_t* fbits,
+                       const uint64_t* pin, const uint64_t* cin, uint64_t* pout, uint64_t* cout, int64_t seg_end,
+                       int32_t* parent, int32_t* depth, uint64_t* nbits, uint64_t* visited, uint64_t* vprev,
+                       int32_t next_depth, int serial_len, uint64_t* slot);
 // Hub ranks: hist[min(deg, nbins-1)] counts the vertices with edges; the hubs
 // are the vertices of degree >= thr (fewer than HUB_BITS); mask (W words),
 // hbase (W) and partial (scan scratch) are temporaries; hubid receives the
@@ -159,6 +175,11 @@ int launch_bitmap_to_queue(const Launch& L, const uint64_t* bits, int64_t W, int
                            int64_t* partial);
 void launch_merge(const Launch& L, bool min_mode, uint64_t* visited, uint64_t* vprev, uint64_t* claim,
                   uint64_t* fnext, int64_t W);
+// the merge of a benign-race top-down level: also the exact next-frontier
+// size (slot S_DISTINCT) and edge count (S_MDISTINCT)
+template <typename OffT>
+void launch_merge_exact(const Launch& L, const OffT* off, const uint64_t* visited, uint64_t* vprev, uint64_t* fnext,
+                        int64_t W, uint64_t* slot);
 
 // ---- multi-source --------------------------------------------------------
 // NNEXT, MNEXT, MFULL and EXAM are spread over the slot's lines; QLEN, OR and
@@ -180,6 +201,27 @@ void launch_ms_bu(const Launch& L, const OffT* off, const int32_t* cols, int64_t
                   uint64_t* visited, uint64_t full, const uint64_t* active_dev, int32_t* par_vm, uint16_t* lvl_vm,
                   uint16_t level, int serial, uint64_t* slot, uint64_t* zslot);
 void launch_ms_mask_to_queue(const Launch& L, const uint64_t* N, int64_t n, int32_t* q, uint64_t* qlen);
+// persistent multi-source top-down engine: inputs, and the state it leaves
+struct MsIn {
+    int64_t qlen, n_f, m_f, m_u, level;
+};
+struct MsState {
+    int64_t qlen, n_f, m_f, m_u, level;
+    int64_t levels_done, reason, reached, examined;
+    int64_t swapped;   // 1: the frontier masks are now in the array passed as N (and F is clear)
+};
+template <typename OffT>
+int ms_persist_max_groups();
+// F holds the frontier masks (non-zero exactly for qa's qlen entries), N is
+// zero.  ctr (SLOTS * SLOT_WORDS words) and ctl zero at launch; rec: 5 int64
+// per level (n_f, m_f, m_u, n_next, entries examined); hring: the host's
+// counter ring, left cleared except the last level's source bits (M_OR)
+template <typename OffT>
+void launch_ms_persist(const Launch& L, int groups, const OffT* off, const int32_t* cols, int64_t n, uint64_t full,
+                       uint64_t* F, uint64_t* N, uint64_t* visited, int32_t* qa, int32_t* qb, int32_t* par_vm,
+                       uint16_t* lvl_vm, uint64_t* hubmark, int serial, MsIn in, MsState* st, uint64_t* ctr,
+                       PersistCtl* ctl, int64_t* rec, int rec_cap, double alpha, int64_t edge_cap,
+                       int64_t max_levels, uint64_t* hring);
 void launch_ms_clear_queue(const Launch& L, const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host,
                            uint64_t* M);
 void launch_ms_output(const Launch& L, int64_t n, int k, const int64_t* src, const uint64_t* visited,
@@ -190,11 +232,15 @@ void launch_ms_output(const Launch& L, int64_t n, int k, const int64_t* src, con
 struct BlockArgs {
     int64_t nrows, ncols, col_base, nzc, nzr, nnz;
     bool sorted;   // entries ascending inside every column and row
+    // top-down union of the frontier columns: -1 accumulator only, 0 chosen
+    // by the expected entry count, 1 sorted union whenever it fits
+    int sort_union;
     const int32_t *jc, *ir, *jr, *ic;
     const int64_t *cp, *rp;
 };
 struct BlockWs {
-    uint64_t* header;   // 8 words cleared per call: [0] qlen, [1] total, [2..4] range
+    uint64_t* header;   // 8 words cleared per call: [0] qlen, [1] total, [2..4] range, [5] skip
+    uint64_t* skip;     // set by the sorted union when it wrote the output
     uint64_t* qlen;
     int64_t* total;
     uint64_t* range;

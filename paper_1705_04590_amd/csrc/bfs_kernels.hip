@@ -277,6 +277,14 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
                 } else if (MODE == CLAIM_CAS) {
                     won[k] = atomicCAS(&parent[v], -1, uu[k]) == -1;
                     if (won[k]) atomicOr((unsigned long long*)&visited[v >> 6], (unsigned long long)bit);
+                } else if (MODE == CLAIM_BENIGN) {
+                    // benign race (Section 5.2): no test, the last parent
+                    // written stays; the bit is set by an atomic whose old
+                    // value is not waited for, so later probes skip v
+                    won[k] = true;
+                    parent[v] = uu[k];
+                    __hip_atomic_fetch_or((unsigned long long*)&visited[v >> 6], (unsigned long long)bit,
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 } else {
                     const uint64_t old = atomicOr((unsigned long long*)&visited[v >> 6], (unsigned long long)bit);
                     won[k] = !(old & bit);
@@ -294,8 +302,11 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
                 my_n += 1;
                 my_m += (uint64_t)dv;
             }
-            // vertices without out-edges are discovered but never expanded
-            const bool push = won[k] && dv > 0;
+            // vertices without out-edges are discovered but never expanded.
+            // The benign race queues nothing: a child may be taken by several
+            // threads, so its copies could outnumber the queue's n entries;
+            // the next frontier comes from the level's merge instead (exact)
+            const bool push = MODE != CLAIM_BENIGN && won[k] && dv > 0;
             const uint64_t wm = __ballot(push);
             if (wm) {
                 const int leader = __ffsll((unsigned long long)wm) - 1;
@@ -336,6 +347,7 @@ void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t*
                        qnext, slot, zslot, next_depth)
     if (mode == CLAIM_MIN) BFS_EXPAND(CLAIM_MIN);
     else if (mode == CLAIM_CAS) BFS_EXPAND(CLAIM_CAS);
+    else if (mode == CLAIM_BENIGN) BFS_EXPAND(CLAIM_BENIGN);
     else BFS_EXPAND(CLAIM_BITMAP);
 #undef BFS_EXPAND
 }
@@ -391,6 +403,40 @@ __global__ void k_merge_any(const uint64_t* __restrict__ visited, uint64_t* __re
         fnext[i] = v & ~p;
         if (v != p) vprev[i] = v;
     }
+}
+
+// Benign-race top-down levels: the same merge, plus the exact size of the
+// next frontier (new bits, S_DISTINCT) and its edge count (S_MDISTINCT, the
+// degrees of the new vertices), since the expansion counted every copy.
+template <typename OffT>
+__global__ __launch_bounds__(256) void k_merge_exact(const OffT* __restrict__ off,
+                                                     const uint64_t* __restrict__ visited,
+                                                     uint64_t* __restrict__ vprev, uint64_t* __restrict__ fnext,
+                                                     int64_t W, uint64_t* __restrict__ slot) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint64_t cnt = 0, deg = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < W; i += stride) {
+        const uint64_t v = visited[i], p = vprev[i];
+        uint64_t x = v & ~p;
+        fnext[i] = x;
+        cnt += (uint64_t)__popcll(x);
+        while (x) {
+            const int b = __ffsll((unsigned long long)x) - 1;
+            x &= x - 1;
+            const int64_t u = i * 64 + b;
+            deg += (uint64_t)((int64_t)off[u + 1] - (int64_t)off[u]);
+        }
+        if (v != p) vprev[i] = v;
+    }
+    uint64_t* ln = slot_line(slot);
+    block_add3<256 / WAVE>(cnt, deg, 0, &ln[S_DISTINCT], &ln[S_MDISTINCT], nullptr);
+}
+
+template <typename OffT>
+void launch_merge_exact(const Launch& L, const OffT* off, const uint64_t* visited, uint64_t* vprev, uint64_t* fnext,
+                        int64_t W, uint64_t* slot) {
+    hipLaunchKernelGGL(k_merge_exact<OffT>, dim3(grid_for(W, 256, L.grid_cap * 4)), dim3(256), 0, L.stream, off,
+                       visited, vprev, fnext, W, slot);
 }
 
 __global__ void k_merge_claim(uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev,
@@ -472,7 +518,9 @@ void launch_validate_csr(const Launch& L, const OffT* off, const int32_t* cols, 
                                       int32_t*, int32_t*, uint64_t*, uint64_t*, int32_t*, uint64_t*,            \
                                       uint64_t*, int32_t);                                                      \
     template void launch_validate_csr<T>(const Launch&, const T*, const int32_t*, int64_t, int64_t, uint32_t,  \
-                                         uint32_t*);
+                                         uint32_t*);                                                              \
+    template void launch_merge_exact<T>(const Launch&, const T*, const uint64_t*, uint64_t*, uint64_t*, int64_t, \
+                                        uint64_t*);
 BFS_INST(int32_t)
 BFS_INST(int64_t)
 

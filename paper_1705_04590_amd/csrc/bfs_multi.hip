@@ -507,6 +507,284 @@ __global__ __launch_bounds__(256) void k_ms_output(int64_t n, int k, const int64
     }
 }
 
+// ---------------------------------------------------------------- persistent engine
+// Consecutive top-down levels of a small batched frontier inside one launch
+// (the multi-source counterpart of the single-source engine in
+// bfs_persist.hip): G resident workgroups, bounded grid barriers between the
+// phases of a level, and the Section 4.4 rule applied on the device.  Level:
+//   A  expand: workgroup g takes the chunk [g C, (g+1) C) of the frontier
+//      queue, spreads its rows' edges over its threads (prefix sum in LDS),
+//      and ORs F[u] & ~visited[v] into N[v]; the thread that turns N[v] from
+//      zero to non-zero queues v                             -- barrier
+//   B  resolve: the new queue is split the same way; each v takes its
+//      minimum-id parents by scanning its sorted row for the first supplier
+//      of every new bit (rows longer than MS_HUB_ROW are marked instead and
+//      get them from the frontier side in B2); visited[v] |= N[v]; counts
+//                                                            -- barrier
+//   B2 (a long row was marked) every frontier edge into a marked v offers u
+//      to each bit of F[u] new at v; the minimum stays; marks cleared
+//                                                            -- barrier
+//   C  the frontier masks of the old queue are cleared: that array is the
+//      next level's N; the level's totals decide whether to go on
+//                                                            -- barrier
+// Every array a phase reads was written before the barrier that opens the
+// phase (writes are released and reads acquired at device scope there).
+// The output (par_vm, lvl_vm, visited) is the same as the per-level kernels'.
+constexpr int MP_BLOCK = 256;
+constexpr int MP_WIN = 1024;   // LDS queue buffer per workgroup
+
+__device__ __forceinline__ bool mp_sync(PersistCtl* ctl, uint32_t G, uint32_t& nbar, long long ticks) {
+    const bool ok = grid_sync(ctl, G, nbar++, ticks);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok;
+}
+
+template <typename OffT>
+__global__ __launch_bounds__(MP_BLOCK) void k_ms_persist(
+    const OffT* __restrict__ off, const int32_t* __restrict__ cols, int64_t n, uint64_t full, uint64_t* Fa,
+    uint64_t* Na, uint64_t* __restrict__ visited, int32_t* qa, int32_t* qb, int32_t* __restrict__ par_vm,
+    uint16_t* __restrict__ lvl_vm, uint64_t* __restrict__ hubmark, int serial, MsIn in, MsState* __restrict__ st,
+    uint64_t* __restrict__ ctr, PersistCtl* __restrict__ ctl, int64_t* __restrict__ rec, int rec_cap, double alpha,
+    int64_t edge_cap, int64_t max_levels, long long roll_ticks, long long bar_ticks, uint64_t* __restrict__ hring) {
+    __shared__ int32_t s_u[MP_BLOCK];
+    __shared__ int64_t s_row[MP_BLOCK];
+    __shared__ uint64_t s_f[MP_BLOCK];
+    __shared__ int64_t s_pre[MP_BLOCK + 1];
+    __shared__ int64_t s_wsum[MP_BLOCK / WAVE];
+    __shared__ int32_t s_win[MP_WIN];
+    __shared__ int s_nw;
+    __shared__ uint64_t s_base;
+    const uint32_t G = gridDim.x, g = blockIdx.x;
+    const int tid = threadIdx.x, lane = lane_id();
+    if (!roll_call(ctl, G, roll_ticks)) return;   // nothing touched yet
+
+    int64_t qlen = in.qlen, n_f = in.n_f, m_f = in.m_f, m_u = in.m_u;
+    int32_t level = (int32_t)in.level;
+    uint64_t *F = Fa, *N = Na;
+    int32_t *qcur = qa, *qnext = qb;
+    int64_t done = 0, reason = ENG_EMPTY, reached = 0, examined = 0;
+    uint64_t last_or = 0;
+    uint32_t nbar = 0;
+    bool fail = false;
+
+    // the edges of this workgroup's queue chunk, MP_BLOCK rows at a time:
+    // visit(u, v, f) for every edge (u, v), f = F[u]; all threads call it together
+    auto for_chunk_edges = [&](int64_t i_beg, int64_t i_end, auto&& visit) {
+        for (int64_t c0 = i_beg; c0 < i_end; c0 += MP_BLOCK) {
+            const int64_t i = c0 + tid;
+            int64_t d = 0;
+            if (i < i_end) {
+                const int32_t u = ld_dev(&qcur[i]);
+                const int64_t b = (int64_t)off[u];
+                d = (int64_t)off[u + 1] - b;
+                s_u[tid] = u;
+                s_row[tid] = b;
+                s_f[tid] = ld_dev(&F[u]);
+            }
+            const int64_t inc = wave_incl_scan(d);
+            if (lane == WAVE - 1) s_wsum[tid / WAVE] = inc;
+            __syncthreads();
+            int64_t before = 0;
+            for (int k = 0; k < tid / WAVE; ++k) before += s_wsum[k];
+            s_pre[tid] = before + inc - d;
+            if (tid == MP_BLOCK - 1) s_pre[MP_BLOCK] = before + inc;
+            __syncthreads();
+            const int nv = (int)min((int64_t)MP_BLOCK, i_end - c0);
+            const int64_t E = s_pre[nv];
+            for (int64_t e0 = 0; e0 < E; e0 += MP_BLOCK) {
+                const int64_t e = e0 + tid;
+                int32_t u = 0, v = -1;
+                uint64_t f = 0;
+                if (e < E) {
+                    int lo = 0, hi = nv - 1;   // last row whose edges start at or before e
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_pre[mid] <= e) lo = mid; else hi = mid - 1;
+                    }
+                    u = s_u[lo];
+                    v = cols[s_row[lo] + (e - s_pre[lo])];
+                    f = s_f[lo];
+                }
+                visit(u, v, f);
+            }
+            __syncthreads();
+        }
+    };
+
+    for (;;) {
+        if (done >= max_levels) { reason = ENG_LEVEL_CAP; break; }
+        if (done > 0 && (double)m_f * alpha > (double)m_u) { reason = ENG_TO_BU; break; }
+        if (m_f > edge_cap) { reason = ENG_EDGE_CAP; break; }
+        uint64_t* slot = ctr + (size_t)(done % SLOTS) * SLOT_WORDS;
+        const uint16_t next_level = (uint16_t)(level + 1);
+        const int64_t C = (qlen + G - 1) / G;
+        const int64_t i_beg = min(qlen, (int64_t)g * C), i_end = min(qlen, i_beg + C);
+        // ---- A: expand
+        if (tid == 0) s_nw = 0;
+        __syncthreads();
+        for_chunk_edges(i_beg, i_end, [&](int32_t u, int32_t v, uint64_t f) {
+            (void)u;
+            bool push = false;
+            if (v >= 0) {
+                const uint64_t x = f & ~ld_dev(&visited[v]);
+                if (x) push = atomicOr((unsigned long long*)&N[v], (unsigned long long)x) == 0ull;
+            }
+            if (push) s_win[atomicAdd(&s_nw, 1)] = v;
+            __syncthreads();
+            const int nw = s_nw;
+            if (nw > MP_WIN - MP_BLOCK) {
+                if (tid == 0) s_base = atomicAdd((unsigned long long*)&slot[M_QLEN], (unsigned long long)nw);
+                __syncthreads();
+                for (int j = tid; j < nw; j += MP_BLOCK) qnext[s_base + j] = s_win[j];
+                __syncthreads();
+                if (tid == 0) s_nw = 0;
+                __syncthreads();
+            }
+        });
+        {
+            const int nw = s_nw;
+            if (tid == 0 && nw) s_base = atomicAdd((unsigned long long*)&slot[M_QLEN], (unsigned long long)nw);
+            __syncthreads();
+            for (int j = tid; j < nw; j += MP_BLOCK) qnext[s_base + j] = s_win[j];
+        }
+        if (!mp_sync(ctl, G, nbar, bar_ticks)) { fail = true; break; }
+        // ---- B: resolve the new vertices' parents
+        const int64_t nq = (int64_t)ld_dev(&slot[M_QLEN]);
+        const int64_t Cq = (nq + G - 1) / G;
+        const int64_t r_beg = min(nq, (int64_t)g * Cq), r_end = min(nq, r_beg + Cq);
+        uint64_t cn = 0, cm = 0, cor = 0, cfull = 0, cx = 0;
+        for (int64_t c0 = r_beg; c0 < r_end; c0 += MP_BLOCK) {
+            const int64_t i = c0 + tid;
+            int64_t v = 0, beg = 0, end = 0;
+            uint64_t need = 0;
+            if (i < r_end) {
+                v = ld_dev(&qnext[i]);
+                need = ld_dev(&N[v]);
+                beg = (int64_t)off[v];
+                end = (int64_t)off[v + 1];
+            }
+            uint64_t scan_need = need;
+            if (i < r_end && need && end - beg > MS_HUB_ROW) {
+                atomicOr((unsigned long long*)&hubmark[v >> 6], 1ull << (v & 63));
+                uint64_t b = need;
+                while (b) {
+                    const int j = __ffsll((unsigned long long)b) - 1;
+                    b &= b - 1;
+                    par_vm[v * 64 + j] = 0x7fffffff;
+                    lvl_vm[v * 64 + j] = next_level;
+                }
+                atomicAdd((unsigned long long*)&slot[M_HUBS], 1ull);
+                scan_need = 0;
+            }
+            int64_t ex = 0;
+            first_suppliers(cols, F, v, beg, end, scan_need, serial, par_vm, lvl_vm, next_level, &ex);
+            if (i < r_end) {
+                const uint64_t vis = ld_dev(&visited[v]) | need;
+                visited[v] = vis;
+                cn += 1;
+                cm += (uint64_t)(end - beg);
+                cor |= need;
+                cx += (uint64_t)ex;
+                if (vis == full) cfull += (uint64_t)(end - beg);
+            }
+        }
+        or_reduce_add(cn, cm, cor, cfull, cx, slot);
+        if (!mp_sync(ctl, G, nbar, bar_ticks)) { fail = true; break; }
+        // ---- B2: long rows take their parents from the frontier side
+        if (ld_dev(&slot[M_HUBS])) {
+            for_chunk_edges(i_beg, i_end, [&](int32_t u, int32_t v, uint64_t f) {
+                if (v < 0 || !((ld_dev(&hubmark[v >> 6]) >> (v & 63)) & 1ull)) return;
+                uint64_t b = f & ld_dev(&N[v]);
+                while (b) {
+                    const int j = __ffsll((unsigned long long)b) - 1;
+                    b &= b - 1;
+                    atomicMin(&par_vm[(int64_t)v * 64 + j], u);
+                }
+            });
+            if (!mp_sync(ctl, G, nbar, bar_ticks)) { fail = true; break; }
+            for (int64_t i = r_beg + tid; i < r_end; i += MP_BLOCK) {
+                const int32_t v = ld_dev(&qnext[i]);
+                atomicAnd((unsigned long long*)&hubmark[v >> 6], ~(1ull << (v & 63)));
+            }
+        }
+        // ---- C: the old frontier masks become the next N (cleared); totals
+        for (int64_t i = i_beg + tid; i < i_end; i += MP_BLOCK) F[ld_dev(&qcur[i])] = 0ull;
+        int64_t n_next = 0, m_next = 0, mfull = 0, exam = 0;
+        for (int j = 0; j < SLOT_SPREAD; ++j) {
+            n_next += (int64_t)ld_dev(&slot[j * SLOT_LINE + M_NNEXT]);
+            m_next += (int64_t)ld_dev(&slot[j * SLOT_LINE + M_MNEXT]);
+            mfull += (int64_t)ld_dev(&slot[j * SLOT_LINE + M_MFULL]);
+            exam += (int64_t)ld_dev(&slot[j * SLOT_LINE + M_EXAM]);
+        }
+        last_or = ld_dev(&slot[M_OR]);
+        // the slot of the level after next was last read at the previous level
+        if (g == 0) {
+            uint64_t* zs = ctr + (size_t)((done + 1) % SLOTS) * SLOT_WORDS;
+            for (int j = tid; j < SLOT_WORDS; j += MP_BLOCK) zs[j] = 0;
+        }
+        if (g == 0 && tid == 0 && done < rec_cap) {
+            int64_t* r = rec + done * 5;
+            r[0] = n_f; r[1] = m_f; r[2] = m_u; r[3] = n_next; r[4] = m_f + exam;
+        }
+        if (!mp_sync(ctl, G, nbar, bar_ticks)) { fail = true; break; }
+        reached += n_next;
+        examined += m_f + exam;
+        ++done;
+        ++level;
+        { uint64_t* t = F; F = N; N = t; }
+        { int32_t* t = qcur; qcur = qnext; qnext = t; }
+        qlen = nq;
+        if (n_next == 0) { n_f = 0; m_f = 0; reason = ENG_EMPTY; break; }
+        m_u -= mfull;
+        n_f = n_next;
+        m_f = m_next;
+    }
+    if (g == 0) {
+        // the host's counter ring continues after the engine: cleared, with
+        // the last level's new-source bits where the next level reads them
+        __syncthreads();
+        for (int j = tid; j < SLOTS * SLOT_WORDS; j += MP_BLOCK) hring[j] = 0;
+        __syncthreads();
+        if (tid == 0) {
+            if (done > 0) hring[(size_t)((level + SLOTS - 1) % SLOTS) * SLOT_WORDS + M_OR] = last_or;
+            st->levels_done = done;
+            st->reason = fail ? ENG_TIMEOUT : reason;
+            st->reached = reached;
+            st->examined = examined;
+            st->qlen = qlen;
+            st->n_f = n_f;
+            st->m_f = m_f;
+            st->m_u = m_u;
+            st->level = level;
+            st->swapped = (F != Fa) ? 1 : 0;
+        }
+    }
+}
+
+template <typename OffT>
+int ms_persist_max_groups() {
+    int dev = 0, nb = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_ms_persist<OffT>, MP_BLOCK, 0) !=
+        hipSuccess || nb < 1)
+        return 1;
+    return nb * p.multiProcessorCount;
+}
+
+template <typename OffT>
+void launch_ms_persist(const Launch& L, int groups, const OffT* off, const int32_t* cols, int64_t n, uint64_t full,
+                       uint64_t* F, uint64_t* N, uint64_t* visited, int32_t* qa, int32_t* qb, int32_t* par_vm,
+                       uint16_t* lvl_vm, uint64_t* hubmark, int serial, MsIn in, MsState* st, uint64_t* ctr,
+                       PersistCtl* ctl, int64_t* rec, int rec_cap, double alpha, int64_t edge_cap,
+                       int64_t max_levels, uint64_t* hring) {
+    // 100 MHz device clock: 2 ms to assemble, 2 s per barrier at most
+    const long long roll_ticks = 200000, bar_ticks = 200000000;
+    hipLaunchKernelGGL(k_ms_persist<OffT>, dim3(groups), dim3(MP_BLOCK), 0, L.stream, off, cols, n, full, F, N,
+                       visited, qa, qb, par_vm, lvl_vm, hubmark, serial, in, st, ctr, ctl, rec, rec_cap, alpha,
+                       edge_cap, max_levels, roll_ticks, bar_ticks, hring);
+}
+
 // ---------------------------------------------------------------- launchers
 template <typename OffT>
 void launch_ms_init(const Launch& L, const OffT* off, int64_t n, int k, const int64_t* src, const uint64_t* iso,
@@ -644,5 +922,14 @@ void launch_ms_output(const Launch& L, int64_t n, int k, const int64_t* src, con
                                   uint64_t*, uint64_t*);
 MS_INST(int32_t)
 MS_INST(int64_t)
+
+#define MP_INST(T)                                                                                                  \
+    template int ms_persist_max_groups<T>();                                                                       \
+    template void launch_ms_persist<T>(const Launch&, int, const T*, const int32_t*, int64_t, uint64_t, uint64_t*, \
+                                       uint64_t*, uint64_t*, int32_t*, int32_t*, int32_t*, uint16_t*, uint64_t*,   \
+                                       int, MsIn, MsState*, uint64_t*, PersistCtl*, int64_t*, int, double,         \
+                                       int64_t, int64_t, uint64_t*);
+MP_INST(int32_t)
+MP_INST(int64_t)
 
 }  // namespace bfsk

@@ -47,67 +47,6 @@ constexpr int PT_BLOCK = 256;
 constexpr int PT_WIN = 1024;             // LDS winner buffer per workgroup
 constexpr int PT_TILE = TD_TILE;         // edges per tile of an edge-balanced level
 constexpr int PT_BAL_AVG = 16;           // average frontier degree from which levels are edge-balanced
-constexpr uint32_t ROLL_POISON = 1u << 30;
-
-template <typename T>
-__device__ __forceinline__ T ld_dev(const T* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Roll call: true when all G workgroups arrived before the deadline (then all
-// of them see true), false when the count was poisoned (then all see false).
-__device__ bool roll_call(PersistCtl* ctl, uint32_t G, long long ticks) {
-    __shared__ int s_ok;
-    if (threadIdx.x == 0) {
-        const uint32_t old = atomicAdd(&ctl->roll, 1u);
-        int ok = -1;
-        if (old & ROLL_POISON) ok = 0;
-        const long long t0 = wall_clock64();
-        while (ok < 0) {
-            const uint32_t c = ld_dev(&ctl->roll);
-            if (c & ROLL_POISON) { ok = 0; break; }
-            if (c >= G) { ok = 1; break; }
-            if (wall_clock64() - t0 > ticks) {
-                // poison only a count that is still short; if the last
-                // workgroup arrived meanwhile the exchange fails and the
-                // next read sees G
-                if (atomicCAS(&ctl->roll, c, c | ROLL_POISON) == c) ok = 0;
-            } else {
-                __builtin_amdgcn_s_sleep(2);
-            }
-        }
-        s_ok = ok;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
-    return s_ok == 1;
-}
-
-// Grid barrier number `k` (0, 1, 2, ...): false on timeout (error flag set).
-__device__ bool grid_sync(PersistCtl* ctl, uint32_t G, uint32_t k, long long ticks) {
-    __shared__ int s_ok;
-    __syncthreads();
-    if (G == 1) return true;
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        atomicAdd(&ctl->bar, 1u);
-        const uint32_t target = G * (k + 1);
-        const long long t0 = wall_clock64();
-        int ok = 1;
-        while (ld_dev(&ctl->bar) < target) {
-            if (ld_dev(&ctl->err) || wall_clock64() - t0 > ticks) {
-                atomicOr(&ctl->err, 1u);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        s_ok = ok;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
-    return s_ok != 0;
-}
 
 template <typename OffT, int MODE>
 __global__ __launch_bounds__(PT_BLOCK) void k_td_persist(

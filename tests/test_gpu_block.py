@@ -154,10 +154,50 @@ def test_accumulator_is_reset_between_calls(orc):
     blk = graphgen.csr_block(off, cols, 0, n // 2, n // 2, n // 2)
     db = DevBlock(blk, n // 2, n // 2, 0, n // 2)
     for seed in range(6):
+        # accumulator and sorted union alternate on the same workspace
+        bfs.bfs_block_set_union(db.g, -1 if seed % 2 == 0 else 1)
         fr = graphgen.random_sorted_subset(n // 2, 50 * (seed + 1), seed=seed)
         r, p = db.td(fr)
         er, ep = orc.block_td(n // 2, n // 2, db.erow, db.ecol, n // 2, fr)
         assert np.array_equal(r, er) and np.array_equal(p, ep)
+
+
+@pytest.mark.parametrize("mode", [-1, 0, 1])
+def test_union_modes_match_oracle(orc, mode):
+    """bfs_block_set_union: the accumulator (-1), the choice by density (0)
+    and the sorted union whenever it fits (1) give the oracle's pairs on
+    frontiers from one column to an eighth of the block; columns holding
+    more than the sorted union's 8192 entries fall back to the accumulator,
+    and the call after such a fallback is unaffected."""
+    scale = 18
+    n = 1 << scale
+    R = C = n // 8
+    blk = graphgen.kronecker_block(scale, 0, R, C, C, seed=1)
+    db = DevBlock(blk, R, C, 0, C)
+    bfs.bfs_block_set_union(db.g, mode)
+    lens = np.diff(blk["cp"])
+    heavy = np.sort(blk["jc"][np.argsort(lens)[::-1][:64]]).astype(np.int32)
+    assert lens[np.isin(blk["jc"], heavy)].sum() > 8192
+    frontiers = [graphgen.random_sorted_subset(C, k, seed=10 + k) for k in (1, 7, 60, 500, 3000, C // 8)]
+    frontiers += [heavy, heavy[:1], np.zeros(0, np.int32), graphgen.random_sorted_subset(C, 40, seed=3)]
+    for fr in frontiers:
+        r, p = db.td(fr)
+        er, ep = orc.block_td(R, C, db.erow, db.ecol, C, fr)
+        assert np.array_equal(r, er) and np.array_equal(p, ep), fr.size
+
+
+def test_union_mode_errors():
+    g = json.load(open(os.path.join(GOLDEN, "fig2_block.json")))
+    ent = np.array(g["entries_row_col"])
+    db = DevBlock(graphgen.coo_block(6, 6, ent[:, 0], ent[:, 1]), 6, 6)
+    with pytest.raises(bfs.BfsError) as e:
+        bfs.bfs_block_set_union(db.g, 2)
+    assert e.value.status == 1
+    off, cols = graphgen.kronecker(8, seed=1)
+    g2 = bfs.bfs_create_graph_csr(t64(off), t32(cols), bfs.BFS_GRAPH_SYMMETRIC)
+    with pytest.raises(bfs.BfsError) as e:
+        bfs.bfs_block_set_union(g2, 0)
+    assert e.value.status == 1
 
 
 def test_block_errors():

@@ -158,8 +158,59 @@ def test_multi_long_rows_get_minimum_parents(orc):
     mg = MG(off, cols)
     srcs = [int(x) for x in rng.choice(np.flatnonzero(np.diff(off) > 0), 60, replace=False)] + [0, leaves + 1]
     for direction in (0, 1):
-        p, d, _ = mg.multi(srcs, dir=direction)
-        check_all(orc, mg, srcs, p, d)
+        # persistent engine on (the default) and off: both mark the long rows
+        for engine in (0, -1):
+            p, d, _ = mg.multi(srcs, dir=direction, small_edges=engine)
+            check_all(orc, mg, srcs, p, d)
+
+
+# (small_edges, persist_edges, persist_groups): engine off, default, tiny and
+# huge edge caps, one workgroup, counts that do not divide the queue evenly
+MS_ENGINE = ((-1, 0, 0), (0, 0, 0), (0, 1, 0), (0, 100, 3), (0, 1 << 30, 1), (0, 1 << 30, 64), (0, 5000, 7))
+
+
+@pytest.mark.parametrize("name", ["kron12", "grid", "er"])
+def test_multi_engine_invariance(orc, name):
+    """The persistent multi-source engine runs small top-down levels in one
+    launch.  Switched off, on with any edge cap or workgroup count, it gives
+    the same parents and depths (the oracle's) and the same per-level
+    schedule and counts."""
+    off, cols = GRAPHS[name]()
+    mg = MG(off, cols)
+    srcs = list(graphgen.random_sources(off, 33, seed=12))
+    ref = None
+    for direction in (0, 1):
+        base = None
+        for eng, cap, grp in MS_ENGINE:
+            p, d, st = mg.multi(srcs, dir=direction, small_edges=eng, persist_edges=cap, persist_groups=grp)
+            if ref is None:
+                check_all(orc, mg, srcs, p, d)
+                ref = (p, d)
+            assert np.array_equal(p, ref[0]) and np.array_equal(d, ref[1]), (direction, eng, cap, grp)
+            L = min(st.levels, bfs.STATS_MAX_LEVELS)
+            sig = (st.levels, st.edges_examined, list(st.level_dir[:L]), list(st.level_nf[:L]),
+                   list(st.level_mf[:L]), list(st.level_mu[:L]), list(st.level_examined[:L]))
+            base = base or sig
+            assert sig == base, (direction, eng, cap, grp)
+
+
+def test_multi_engine_on_a_long_grid():
+    """A 3 x 2000 grid from its corners and middle: about 2000 levels, all
+    inside the engine, checked against the closed form."""
+    H, W = 3, 2000
+    off, cols = graphgen.grid2d(H, W)
+    mg = MG(off, cols)
+    srcs = [0, W - 1, (H - 1) * W, H * W - 1, W // 2, W + 700]
+    r, c = np.divmod(np.arange(H * W), W)
+    for eng in (0, -1):
+        p, d, st = mg.multi(srcs, small_edges=eng)
+        for j, s in enumerate(srcs):
+            r0, c0 = divmod(s, W)
+            dist = np.abs(r - r0) + np.abs(c - c0)
+            par = np.where(r > r0, (r - 1) * W + c, np.where(c > c0, r * W + c - 1,
+                                                            np.where(c < c0, r * W + c + 1, (r + 1) * W + c)))
+            par[s] = s
+            assert np.array_equal(d[j], dist) and np.array_equal(p[j], par), (eng, j)
 
 
 def test_multi_level_cap_is_an_error():

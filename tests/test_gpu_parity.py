@@ -178,6 +178,73 @@ def test_config1_scale16_int32_offsets(orc, graphs):
         check(orc, dg, s, p, d, False, ref)
 
 
+@pytest.mark.parametrize("name", ["kron12", "kron14", "er", "grid", "pieces", "path", "star"])
+@pytest.mark.parametrize("segments", [1, 2, 4, 8])
+def test_column_blocked_bottom_up(orc, graphs, name, segments):
+    """bu_segments = S: the bottom-up sweep probes the row heads, then S
+    sub-steps scan the remaining rows one column segment at a time in
+    ascending order (Alg. 4's sub-steps inside one device).  Minimum parents
+    stay exact and the entries examined equal the oracle's row-order
+    first-hit scan; any-parent searches (hub heads, lazy -1 fill) pass the
+    tree check."""
+    for off_dtype in (np.int32, np.int64):
+        dg = get(graphs, name, off_dtype)
+        for s in sources_for(dg.off, k=2, seed=41):
+            ref = orc.bfs_min(dg.off, dg.cols, int(s))
+            for dirv in (bfs.BFS_DIR_BU, bfs.BFS_DIR_DO):
+                p, d, st = dg.run(s, dir=dirv, parent_mode=bfs.BFS_PARENT_MIN, bu_segments=segments)
+                check(orc, dg, s, p, d, True, ref)
+                for lv in range(min(st.levels, bfs.STATS_MAX_LEVELS)):
+                    if st.level_dir[lv] == 1:
+                        assert st.level_examined[lv] == orc.bu_scan_lengths(dg.off, dg.cols, d, lv)[0]
+                for head in (0, 1, 2, 3):
+                    p, d, st = dg.run(s, dir=dirv, bu_head=head, bu_serial=4, bu_segments=segments)
+                    check(orc, dg, s, p, d, False, ref)
+        # a 64-entry serial limit and 1-entry one (the wave scans the rest)
+        s = sources_for(dg.off, k=1, seed=43)[0]
+        ref = orc.bfs_min(dg.off, dg.cols, int(s))
+        for serial in (1, 64):
+            p, d, _ = dg.run(s, dir=bfs.BFS_DIR_BU, parent_mode=bfs.BFS_PARENT_MIN, bu_serial=serial,
+                             bu_segments=segments)
+            check(orc, dg, s, p, d, True, ref)
+
+
+def test_column_blocked_bad_segment_count():
+    off, cols = path_graph(100)
+    dg = DevGraph(off, cols)
+    with pytest.raises(bfs.BfsError) as e:
+        dg.run(0, bu_segments=9)
+    assert e.value.status == 1
+
+
+@pytest.mark.parametrize("name", ["kron12", "kron14", "er", "grid", "pieces", "star", "complete"])
+def test_benign_race_top_down(orc, graphs, name):
+    """td_claim = 2: children are taken with no atomic test (the benign race
+    of Section 5.2), so several threads may take the same child.  Depths stay
+    exact and parents valid; the next frontier comes from the level's merge,
+    so the per-level frontier sizes and edge counts, and the direction
+    schedule, equal the oracle's; the repeated takes are counted and never
+    exceed the takes."""
+    for off_dtype in (np.int32, np.int64):
+        dg = get(graphs, name, off_dtype)
+        for s in sources_for(dg.off):
+            ref = orc.bfs_min(dg.off, dg.cols, int(s))
+            n_f, m_f, _ = orc.level_stats(dg.off, ref[1])
+            for kw in (dict(dir=bfs.BFS_DIR_TD), dict(dir=bfs.BFS_DIR_TD, small_edges=-1),
+                       dict(dir=bfs.BFS_DIR_DO), dict(dir=bfs.BFS_DIR_DO, small_edges=-1, td_prepass=1),
+                       dict(dir=bfs.BFS_DIR_DO, alpha=1e9, beta=1e9, small_edges=-1)):
+                p, d, st = dg.run(s, td_claim=2, **kw)
+                check(orc, dg, s, p, d, False, ref)
+                L = min(st.levels, bfs.STATS_MAX_LEVELS)
+                assert st.levels == len(n_f)
+                assert list(st.level_nf[:L]) == n_f[:L].tolist()
+                assert list(st.level_mf[:L]) == m_f[:L].tolist()
+                assert 0 <= st.td_duplicates <= st.td_claims
+                if kw.get("small_edges") == -1 and kw["dir"] == bfs.BFS_DIR_TD:
+                    # every level after the source's goes through the expansion
+                    assert st.td_claims - st.td_duplicates == int((d > 0).sum())
+
+
 def test_tuning_knobs_do_not_change_results(orc, graphs):
     dg = get(graphs, "kron14")
     s = int(graphgen.random_sources(dg.off, 1, seed=3)[0])
@@ -199,12 +266,29 @@ def test_outputs_fully_written(orc, graphs, name):
         for s in sources_for(dg.off, k=2, seed=31):
             ref = orc.bfs_min(dg.off, dg.cols, int(s))
             for kw in (dict(), dict(dir=bfs.BFS_DIR_BU), dict(dir=bfs.BFS_DIR_TD), dict(alpha=1e-9),
-                       dict(alpha=1e9, beta=1e9), dict(small_edges=-1), dict(td_claim=1),
+                       dict(alpha=1e9, beta=1e9), dict(small_edges=-1), dict(td_claim=1), dict(td_claim=2),
                        dict(parent_mode=bfs.BFS_PARENT_MIN), dict(td_prepass=1, small_edges=-1),
                        dict(td_prepass=1, small_edges=-1, alpha=1e9, beta=1e9)):
-                p, d, _ = dg.run(s, **kw)
+                p, d, st = dg.run(s, **kw)
                 check(orc, dg, s, p, d, kw.get("parent_mode") == bfs.BFS_PARENT_MIN, ref)
                 assert (p >= -1).all() and (d >= -1).all()
+                # who wrote the -1 fill: initialisation (-1) in the modes that
+                # compare against it, else the first bottom-up sweep or top-down
+                # pre-pass, else a pass after the last level (-2)
+                L = min(st.levels, bfs.STATS_MAX_LEVELS)
+                eager = kw.get("parent_mode") == bfs.BFS_PARENT_MIN or kw.get("td_claim") == 1 or \
+                    kw.get("dir") == bfs.BFS_DIR_TD
+                if eager:
+                    assert st.fill_level == -1
+                elif st.fill_level >= bfs.STATS_MAX_LEVELS:
+                    assert st.fill_level < st.levels   # past the recorded levels
+                elif st.fill_level >= 0:
+                    first_bu = [x for x in range(L) if st.level_dir[x] == 1]
+                    assert st.level_dir[st.fill_level] == 1 or kw.get("td_prepass")
+                    if not kw.get("td_prepass"):
+                        assert st.fill_level == first_bu[0]
+                else:
+                    assert st.fill_level == -2 and st.bu_levels == 0
 
 
 def test_uniform_degree_graph_has_no_hubs(orc):
