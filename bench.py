@@ -105,6 +105,42 @@ def level_bytes(st: dict, row: dict, n: int, wo: int, iso: int):
     return out
 
 
+def ms_level_bytes(st: dict, n: int):
+    """Model bytes of each level of a batched (64-source) search, from the
+    library's per-level counts: 16 B per vertex touched (its visited and
+    frontier masks; a bottom-up level touches every vertex, a top-down level
+    its frontier and the vertices it reaches), 12 B per adjacency entry
+    scanned (the column and the neighbour's mask), 8 B per next-frontier
+    mask.  The 8 B per (vertex, source) output entry belong to the final
+    transpose, not to a level."""
+    L = len(st["level_dir"])
+    out = []
+    for d in range(L):
+        nn = st["level_nf"][d + 1] if d + 1 < L else 0
+        touched = n if st["level_dir"][d] == 1 else st["level_nf"][d] + nn
+        out.append(("ms_bu" if st["level_dir"][d] == 1 else "ms_td",
+                    16 * touched + 12 * st["level_examined"][d] + 8 * nn))
+    return out
+
+
+def ms_roofline(st: dict, n: int, k: int):
+    """Roofline entry of the batched search's bottom-up levels (its dominant
+    kernel), from one batch timed with events around every kernel."""
+    nbytes, ms, launches = 0.0, 0.0, 0
+    for d, (kind, b) in enumerate(ms_level_bytes(st, n)):
+        if kind == "ms_bu" and d < len(st["level_ms"]):
+            nbytes += b
+            ms += st["level_ms"][d]
+            launches += 1
+    if not launches or ms <= 0:
+        return None
+    achieved = nbytes / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "kernel": "ms_bu_sweep", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "launches": launches,
+            "avg_launch_us": round(ms / launches * 1e3, 2), "alg_bytes_per_launch": round(nbytes / launches),
+            "alg_bytes_from": "library per-level counts (frontier sizes, entries scanned)", "sources": k}
+
+
 def read_traffic(kernel: str):
     """Per-launch HBM bytes from the committed PMC summary, if it matches the current kernels."""
     if not os.path.exists(PROFILE_PMC):
@@ -684,6 +720,13 @@ def main():
                 f"({mt['default_ms']:.2f} -> {mt['tuned_ms']:.2f} ms)")
         bfs.bfs_run_multi(g, sources[:k], bpar, bdep, wsm, mopts, stream)
         torch.cuda.synchronize()
+        # one more batch with events around every kernel: the dominant
+        # kernel's (the batched bottom-up sweep's) roofline from the model
+        # bytes of its levels
+        mt_opts = (autotune.opts_from(mt, timing=1) if tuned is not None
+                   else bfs.bfs_opts_default(alpha=args.alpha, beta=args.beta, timing=1))
+        ms_roof = ms_roofline(bfs.bfs_run_multi(g, sources[:k], bpar, bdep, wsm, mt_opts, stream).as_dict(), n, k)
+        torch.cuda.synchronize()
         t_b = time.perf_counter()
         for _ in range(args.batched_reps):
             bfs.bfs_run_multi(g, sources[:k], bpar, bdep, wsm, mopts, stream)
@@ -695,7 +738,8 @@ def main():
                    "single_source_min_queries_per_s": round(single_min_qps, 1),
                    "speedup_vs_single_min": round(k / batch_s / single_min_qps, 3),
                    "single_source_any_queries_per_s": round(single_any_qps, 1),
-                   "speedup_vs_single_any": round(k / batch_s / single_any_qps, 3)}
+                   "speedup_vs_single_any": round(k / batch_s / single_any_qps, 3),
+                   "roofline": ms_roof}
         log(f"[bench] batched: {batch_s * 1e3:.2f} ms per {k}-source batch -> {k / batch_s:.1f} queries/s "
             f"(single-source: {single_min_qps:.1f} q/s minimum parents, {single_any_qps:.1f} q/s any parents)")
         del wsm, bpar, bdep

@@ -153,8 +153,31 @@ typedef struct {
                               so each sub-step probes only its slice (n/(8S)
                               bytes) of the frontier bitmap.  Rows are sorted,
                               so the first hit is the same and minimum parents
-                              stay exact                                        */
-    int32_t reserved[2];
+                              stay exact.  Needs BFS_GRAPH_SORTED               */
+    int32_t td_segments;   /* top-down levels in column blocks: 0 (default) = one
+                              edge-tiled pass over the frontier's rows; S = 1..8
+                              = on levels of at least td_seg_edges frontier
+                              edges, S passes, one per column segment of about
+                              n/S ids,
+                              each over the frontier's entries inside its
+                              segment (found by binary search in the sorted
+                              rows), so each pass probes and claims only its
+                              slice of the visited bitmap.  Needs sorted rows
+                              for the segment bounds; results do not change    */
+    int32_t td_seg_edges;  /* ... on levels of at least this many frontier edges
+                              (0 = default 2^20)                                */
+    /* workgroup and tile shapes (tuning only; results do not change) */
+    int32_t td_block;      /* threads per top-down expand workgroup: 128, 256
+                              or 512 (0 = default 256).  A tile stays 1024
+                              frontier edges, so a thread takes 8, 4 or 2     */
+    int32_t bu_block;      /* threads per bottom-up sweep workgroup: 128, 256
+                              or 512 (0 = default 256), one wave per work
+                              unit; column-blocked levels keep 256             */
+    int32_t bu_group;      /* bottom-up work unit: at most this many 64-vertex
+                              words per wave, a power of two 1..64 (0 = default:
+                              64, halved while the grid would get fewer than
+                              two units per wave; the first sweep of a search
+                              caps it at 8)                                    */
 } bfs_opts;
 
 typedef struct {
@@ -300,15 +323,17 @@ bfs_status bfs_block_td(bfs_graph* g, const int32_t* d_frontier, int64_t nf, int
 
 /* How bfs_block_td (and bfs_block_td_noalloc) unite the frontier's columns
  * (Section 5.2 weighs a sparse accumulator against a heap-based merge):
- *   0  (default) by density: when |F| times the block's mean column length
- *      is at most 8192, one workgroup sorts the columns' (row, parent)
- *      pairs in LDS and keeps each row's smallest parent; when the columns
- *      turn out to hold more than 8192 entries, or the frontier is denser,
- *      the sparse accumulator runs (its ordered pass reads nrows/64 words)
- *   1  the sorted union whenever the entries fit (else the accumulator)
- *  -1  the accumulator only
- * The output is the same in every mode.  Returns BFS_E_INVALID_ARG for a
- * handle that is not a DCSC block or a mode outside [-1, 1].               */
+ *   0  (default) or -1: the sparse accumulator (an atomic minimum per row,
+ *      then an ordered pass over the nrows/64 occupied-bit words)
+ *   1  the sorted union: one workgroup gathers the frontier columns'
+ *      (row, parent) pairs into LDS, sorts them and keeps each row's
+ *      smallest parent, when they are at most 8192; otherwise the
+ *      accumulator runs
+ * The output is the same in every mode.  The accumulator is the default
+ * because it was faster at every density measured on one 2^27 x 2^27 block
+ * of a scale-30 graph (0.042 vs 0.078 ms at |F| = 1342).  Returns
+ * BFS_E_INVALID_ARG for a handle that is not a DCSC block or a mode outside
+ * [-1, 1].                                                                 */
 bfs_status bfs_block_set_union(bfs_graph* g, int mode);
 
 /* Bottom-up local discovery on a DCSC block, one sub-step (Alg. 4): every

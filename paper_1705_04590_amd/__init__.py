@@ -46,7 +46,8 @@ class bfs_opts(ctypes.Structure):
                 ("grid_blocks", ctypes.c_int32), ("td_claim", ctypes.c_int32), ("small_edges", ctypes.c_int32),
                 ("persist_edges", ctypes.c_int32), ("persist_groups", ctypes.c_int32),
                 ("bu_head", ctypes.c_int32), ("td_prepass", ctypes.c_int32), ("bu_segments", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("td_segments", ctypes.c_int32), ("td_seg_edges", ctypes.c_int32), ("td_block", ctypes.c_int32),
+                ("bu_block", ctypes.c_int32), ("bu_group", ctypes.c_int32)]
 
 
 class bfs_stats(ctypes.Structure):

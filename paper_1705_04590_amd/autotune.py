@@ -11,6 +11,13 @@ direction-invariant; the GPU tests check both):
   bu_head       bottom-up probes for ANY parents: automatic (0), row order (1),
                 three highest-degree neighbours (2), two hub-ranked neighbours (3)
   td_prepass    hub pre-pass of heavy top-down levels: default threshold (0) or off (-1)
+  td_segments   top-down levels of at least 2^20 frontier edges in 0 (one pass), 2 or 4
+                column segments
+  td_block      threads per top-down expand workgroup (256, 128, 512; the tile stays
+                1024 edges)
+  bu_block      threads per bottom-up sweep workgroup (256, 128, 512)
+  bu_group      cap on the 64-vertex words of a bottom-up work unit (0 = automatic,
+                8, 16, 32)
 
 The search is a coordinate descent: (alpha, beta) on a grid first, then each
 remaining knob in turn, every candidate timed as the mean wall time of the
@@ -26,7 +33,7 @@ import time
 
 import torch
 
-from . import bfs_opts_default, bfs_run, bfs_run_multi, workspace
+from . import BFS_GRAPH_SORTED, bfs_opts_default, bfs_run, bfs_run_multi, workspace
 
 ALPHAS = (15.0, 4.0, 8.0, 25.0, 40.0, 80.0, 160.0)
 BETAS = (18.0, 6.0, 36.0, 72.0)
@@ -36,6 +43,12 @@ CLAIMS = (0, 1, 2)
 ENGINE = (0, -1)
 HEADS = (0, 1, 2, 3)
 PREPASS = (0, -1)
+TD_SEGMENTS = (0, 2, 4)
+TD_BLOCKS = (0, 128, 512)
+BU_BLOCKS = (0, 128, 512)
+BU_GROUPS = (0, 8, 16, 32)
+KNOBS = ("alpha", "beta", "bu_serial", "grid_blocks", "td_claim", "small_edges", "bu_head", "td_prepass",
+         "td_segments", "td_block", "bu_block", "bu_group")
 
 
 def _key(g, k: int) -> str:
@@ -94,6 +107,8 @@ def tune(g, sources, k: int = 1, cache_path: str | None = None, reps: int = 3, v
 
     best = {"alpha": 15.0, "beta": 18.0, "bu_serial": 16, "grid_blocks": 2048, "td_claim": 0, "small_edges": 0,
             "bu_head": 0, "td_prepass": 0}
+    if k == 1:
+        best.update(td_segments=0, td_block=0, bu_block=0, bu_group=0)
     trials = []
 
     def measure(cfg):
@@ -118,7 +133,10 @@ def tune(g, sources, k: int = 1, cache_path: str | None = None, reps: int = 3, v
                 best, best_t = cfg, t
     for name, values in (("bu_serial", SERIALS), ("grid_blocks", GRIDS), ("td_claim", CLAIMS if k == 1 else ()),
                          ("small_edges", ENGINE if k == 1 else ()), ("bu_head", HEADS if k == 1 else ()),
-                         ("td_prepass", PREPASS if k == 1 else ())):
+                         ("td_prepass", PREPASS if k == 1 else ()),
+                         ("td_segments", TD_SEGMENTS if k == 1 and g.flags & BFS_GRAPH_SORTED else ()),
+                         ("td_block", TD_BLOCKS if k == 1 else ()), ("bu_block", BU_BLOCKS if k == 1 else ()),
+                         ("bu_group", BU_GROUPS if k == 1 else ())):
         for v in values:
             cfg = dict(best, **{name: v})
             if cfg == best:
@@ -145,7 +163,6 @@ def cached(g, k: int, cache_path: str):
 
 
 def opts_from(result: dict, **extra):
-    cfg = {k: result[k] for k in ("alpha", "beta", "bu_serial", "grid_blocks", "td_claim", "small_edges", "bu_head",
-                                  "td_prepass") if k in result}
+    cfg = {k: result[k] for k in KNOBS if k in result}
     cfg.update(extra)
     return bfs_opts_default(**cfg)

@@ -160,7 +160,7 @@ bfs_status readback(HostCtx* c, hipStream_t s, const void* src, int nw, const ui
 // -------------------------------------------------------------- workspace layout
 struct SingleLayout {
     size_t counters, pctl, pctr, small, ctl_end, rec, visited, vprev, fbits, nbits, claim, q0, q1, scan, tiles, partial,
-        hb, pcsum, total;
+        hb, pcsum, segpos, segtot, total;
 };
 
 SingleLayout single_layout(const bfs_graph* g) {
@@ -191,6 +191,10 @@ SingleLayout single_layout(const bfs_graph* g) {
     L.hb = o; o = align_up(o + sizeof(uint64_t) * (HUB_BITS / 64));
     // per-workgroup edge totals of the engine's edge-balanced levels
     L.pcsum = o; o = align_up(o + sizeof(int64_t) * (size_t)(g->persist_groups_max > 0 ? g->persist_groups_max : 1));
+    // top-down column segments: each queue entry's first entry in the
+    // segment, and the segment's edge total
+    L.segpos = o; o = align_up(o + sizeof(int32_t) * (size_t)(n + 1));
+    L.segtot = o; o = align_up(o + sizeof(int64_t));
     L.total = o;
     return L;
 }
@@ -564,15 +568,42 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                     HIP_TRY(T.end(BFS_K_TD_EXPAND, level));
                     if (st) { st->launches[BFS_K_CONVERT] += 1; st->launches[BFS_K_TD_EXPAND] += 1; }
                 }
-                HIP_TRY(T.begin(BFS_K_TD_SCAN));
-                int nl = launch_td_scan<OffT>(L, off, qcur, qlen_dev, qlen, scan, tiles, partial, nullptr);
-                HIP_TRY(hipGetLastError());
-                HIP_TRY(T.end(BFS_K_TD_SCAN, level));
-                HIP_TRY(T.begin(BFS_K_TD_EXPAND));
-                launch_td_expand<OffT>(L, claim_mode, off, g->cols, g->nnz, qcur, qlen_dev, qlen, scan, tiles, m_f,
-                                       parent, depth, visited, claim, qnext, slot, zslot, next_depth);
-                HIP_TRY(hipGetLastError());
-                HIP_TRY(T.end(BFS_K_TD_EXPAND, level));
+                int nl = 0;
+                const int64_t seg_min = o.td_seg_edges > 0 ? o.td_seg_edges : TD_SEG_MIN_EDGES;
+                const int tds = m_f >= seg_min ? o.td_segments : 0;
+                if (tds > 0) {
+                    // column segments in ascending order: each pass expands
+                    // only the frontier's entries inside its id range, so
+                    // its probes and claims touch only that slice of the
+                    // visited bitmap; the claims are exact in every mode,
+                    // so the order does not change the result
+                    int32_t* segpos = (int32_t*)(ws + Lo.segpos);
+                    int64_t* segtot = (int64_t*)(ws + Lo.segtot);
+                    const int64_t segw = (W + tds - 1) / tds;
+                    HIP_TRY(T.begin(BFS_K_TD_EXPAND));
+                    for (int sg = 0; sg < tds; ++sg) {
+                        const int64_t lo = std::min<int64_t>(n, sg * segw * 64);
+                        const int64_t hi = sg == tds - 1 ? n : std::min<int64_t>(n, (sg + 1) * segw * 64);
+                        nl += launch_td_scan_seg<OffT>(L, off, g->cols, qcur, qlen_dev, qlen, lo, hi, scan, tiles,
+                                                       partial, segpos, segtot);
+                        launch_td_expand<OffT>(L, claim_mode, off, g->cols, g->nnz, qcur, qlen_dev, qlen, scan, tiles,
+                                               m_f, parent, depth, visited, claim, qnext, slot, zslot, next_depth,
+                                               segtot, segpos, o.td_block);
+                    }
+                    HIP_TRY(hipGetLastError());
+                    HIP_TRY(T.end(BFS_K_TD_EXPAND, level));
+                } else {
+                    HIP_TRY(T.begin(BFS_K_TD_SCAN));
+                    nl = launch_td_scan<OffT>(L, off, qcur, qlen_dev, qlen, scan, tiles, partial, nullptr);
+                    HIP_TRY(hipGetLastError());
+                    HIP_TRY(T.end(BFS_K_TD_SCAN, level));
+                    HIP_TRY(T.begin(BFS_K_TD_EXPAND));
+                    launch_td_expand<OffT>(L, claim_mode, off, g->cols, g->nnz, qcur, qlen_dev, qlen, scan, tiles,
+                                           m_f, parent, depth, visited, claim, qnext, slot, zslot, next_depth,
+                                           nullptr, nullptr, o.td_block);
+                    HIP_TRY(hipGetLastError());
+                    HIP_TRY(T.end(BFS_K_TD_EXPAND, level));
+                }
                 HIP_TRY(T.begin(BFS_K_CONVERT));
                 fbits_stale = false;
                 if (claim_mode == CLAIM_BENIGN) launch_merge_exact<OffT>(L, off, visited, vprev, fbits, W, slot);
@@ -581,7 +612,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                 HIP_TRY(T.end(BFS_K_CONVERT, level));
                 if (st) {
                     st->launches[BFS_K_TD_SCAN] += nl;
-                    st->launches[BFS_K_TD_EXPAND] += 1;
+                    st->launches[BFS_K_TD_EXPAND] += tds > 0 ? tds : 1;
                     st->launches[BFS_K_CONVERT] += 1;
                 }
             }
@@ -625,7 +656,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             HIP_TRY(T.begin(BFS_K_BU_SWEEP));
             launch_bu_sweep<OffT>(L, hk == 2 ? g->d_hubr : hk == 1 ? g->d_hub : g->d_head, hk, g->d_iso, g->d_nbase,
                                   off, g->cols, fbits, hb, nbits, visited, vprev, parent, depth, W, next_depth, serial,
-                                  slot, zslot, !out_filled, n, src, pend_a);
+                                  slot, zslot, !out_filled, n, src, pend_a, o.bu_block, o.bu_group);
             if (!out_filled) fill_level = level;
             out_filled = true;
             const int64_t segw = segs ? (W + segs - 1) / segs : 0;
@@ -773,10 +804,13 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
     // persistent engine for runs of small top-down levels (the same knobs as
     // the single-source engine: small_edges < 0 switches it off)
     bool engine_on = o.small_edges >= 0;
-    const int64_t eng_cap = o.persist_edges > 0 ? o.persist_edges : 65536;
+    // edge cap of an engine level: the first level of a run is also held to
+    // 2^16 edges and the later ones to rows of at most 4096 entries
+    const int64_t eng_cap = o.persist_edges > 0 ? o.persist_edges : ((int64_t)1 << 18);
     int eng_groups = o.persist_groups > 0 ? o.persist_groups : 64;
     eng_groups = std::max(1, std::min(eng_groups, g->ms_groups_max));
     bool skip_engine = false;
+    int64_t fmaxdeg = -1;   // longest row of the current frontier, -1 when not known
     for (;;) {
         if (level >= 65535) return fail(BFS_E_UNSUPPORTED, "more than 65535 levels");
         if (o.dir == BFS_DIR_TD) cur_dir = 0;
@@ -787,7 +821,10 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
         uint64_t* zslot = counters + (size_t)((level + 1) % SLOTS) * SLOT_WORDS;
         uint64_t* pslot = counters + (size_t)((level + SLOTS - 1) % SLOTS) * SLOT_WORDS;
         const uint16_t next_level = (uint16_t)(level + 1);
-        if (cur_dir == 0 && engine_on && !skip_engine && m_f > 0 && m_f <= eng_cap) {
+        // the engine's own entry test: rows known to be short, or few edges
+        const bool eng_fits = fmaxdeg < 0 ? m_f <= std::min(eng_cap, MS_ENGINE_FIRST_CAP)
+                                          : m_f <= eng_cap && fmaxdeg <= MS_ENGINE_MAX_DEG;
+        if (cur_dir == 0 && engine_on && !skip_engine && m_f > 0 && eng_fits) {
             // the engine needs the frontier as a queue and N clean
             HIP_TRY(T.begin(BFS_K_CONVERT));
             if (!fq_valid) {
@@ -805,7 +842,8 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
             const double eng_alpha = o.dir == BFS_DIR_TD ? 0.0 : o.alpha;
             HIP_TRY(T.begin(BFS_K_MS_LEVEL));
             launch_ms_persist<OffT>(L, eng_groups, off, g->cols, n, full, F, N, visited, qa, qb, par_vm, lvl_vm,
-                                    hubmark, serial, MsIn{qlen, n_f, m_f, m_u, level}, (MsState*)(ws + Lo.mstate),
+                                    hubmark, serial, MsIn{qlen, n_f, m_f, m_u, level, fmaxdeg},
+                                    (MsState*)(ws + Lo.mstate),
                                     (uint64_t*)(ws + Lo.pctr), (PersistCtl*)(ws + Lo.pctl), (int64_t*)(ws + Lo.mrec),
                                     rec_cap, eng_alpha, eng_cap, 65535 - level, counters);
             HIP_TRY(hipGetLastError());
@@ -852,6 +890,7 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
             n_f = es.n_f;
             m_f = es.m_f;
             m_u = es.m_u;
+            fmaxdeg = es.maxdeg;
             fq_valid = true;
             if (es.reason == ENG_EMPTY) break;
             // a cap hit at entry: this level through the per-level kernels
@@ -903,6 +942,9 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
             st->level_examined[level] = lvl_exam;
         }
         if (st) { if (cur_dir == 0) st->td_levels++; else st->bu_levels++; }
+        // the longest row of the next frontier: recorded by a top-down
+        // level's resolve pass, not known after a bottom-up level
+        fmaxdeg = cur_dir == 0 ? (int64_t)slot_max(h, M_SLOT_MAXDEG) : -1;
         // frontier <- next; the old frontier array becomes the next buffer
         uint64_t* t = F; F = N; N = t;
         if (cur_dir == 0) {
@@ -1243,6 +1285,15 @@ bfs_status bfs_run(bfs_graph* g, int64_t source, const bfs_opts* opts, int32_t* 
     if (o.td_claim < 0 || o.td_claim > 2) return fail(BFS_E_INVALID_ARG, "bad td_claim %d", o.td_claim);
     if (o.bu_segments < 0 || o.bu_segments > BU_MAX_SEGMENTS)
         return fail(BFS_E_INVALID_ARG, "bu_segments %d outside [0, %d]", o.bu_segments, BU_MAX_SEGMENTS);
+    if (o.td_seg_edges < 0) return fail(BFS_E_INVALID_ARG, "td_seg_edges %d < 0", o.td_seg_edges);
+    if (o.td_segments < 0 || o.td_segments > TD_MAX_SEGMENTS)
+        return fail(BFS_E_INVALID_ARG, "td_segments %d outside [0, %d]", o.td_segments, TD_MAX_SEGMENTS);
+    if (o.td_block != 0 && o.td_block != 128 && o.td_block != 256 && o.td_block != 512)
+        return fail(BFS_E_INVALID_ARG, "td_block %d not 0, 128, 256 or 512", o.td_block);
+    if (o.bu_block != 0 && o.bu_block != 128 && o.bu_block != 256 && o.bu_block != 512)
+        return fail(BFS_E_INVALID_ARG, "bu_block %d not 0, 128, 256 or 512", o.bu_block);
+    if (o.bu_group < 0 || o.bu_group > WAVE || (o.bu_group & (o.bu_group - 1)))
+        return fail(BFS_E_INVALID_ARG, "bu_group %d not 0 or a power of two up to 64", o.bu_group);
     if (!(o.alpha > 0) || !(o.beta > 0)) return fail(BFS_E_INVALID_ARG, "alpha and beta must be > 0");
     if (source < 0 || source >= g->n)
         return fail(BFS_E_OUT_OF_RANGE, "source %lld outside [0, %lld)", (long long)source, (long long)g->n);
@@ -1254,6 +1305,8 @@ bfs_status bfs_run(bfs_graph* g, int64_t source, const bfs_opts* opts, int32_t* 
         return fail(BFS_E_UNSUPPORTED, "bottom-up levels need a graph created with BFS_GRAPH_SYMMETRIC");
     if (o.dir != BFS_DIR_TD && o.parent_mode == BFS_PARENT_MIN && !(g->flags & BFS_GRAPH_SORTED))
         return fail(BFS_E_UNSUPPORTED, "minimum parents with bottom-up levels need BFS_GRAPH_SORTED");
+    if ((o.bu_segments > 0 || o.td_segments > 0) && !(g->flags & BFS_GRAPH_SORTED))
+        return fail(BFS_E_UNSUPPORTED, "column segments need BFS_GRAPH_SORTED (a segment is a sub-range of a row)");
     if (stats) std::memset(stats, 0, sizeof(*stats));
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess && dev != g->device) {

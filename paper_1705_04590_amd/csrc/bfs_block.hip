@@ -427,12 +427,13 @@ void launch_block_td(const Launch& L, const BlockArgs& B, const int32_t* F, int6
     const int64_t qmax = nf < B.nzc ? nf : B.nzc;
     launch_scan(L.stream, QueueDegree<int64_t>{B.cp, W.q}, W.qlen, qmax, W.partial,
                 TileSink{W.scan, W.tiles, W.total});
-    // hypersparse frontier: when the frontier's columns are expected to hold
-    // at most SORT_CAP entries (|F| times the mean column length), the sorted
-    // union takes the call, unless they hold more (then it leaves the skip
-    // word at 0 and the accumulator runs)
-    const bool sorted_union = B.sort_union >= 0 &&
-                              (B.sort_union == 1 || (double)nf * (double)B.nnz <= (double)SORT_CAP * (double)B.ncols);
+    // the sorted union when asked for (bfs_block_set_union 1): it takes the
+    // call unless the frontier's columns hold more than SORT_CAP entries
+    // (then it leaves the skip word at 0 and the accumulator runs).  Not the
+    // default: measured on one 2^27 x 2^27 block at |F| = 1342, the
+    // accumulator's call took 0.042 ms and the sorted union's 0.078 ms, the
+    // accumulator's ordered pass over nrows/64 words being only a few us
+    const bool sorted_union = B.sort_union == 1;
     if (sorted_union)
         hipLaunchKernelGGL(k_blk_sorted_union, dim3(1), dim3(SORT_BLOCK), 0, L.stream, B.cp, B.jc, B.ir, W.q, W.qlen,
                            W.scan, W.total, B.col_base, out_rows, out_parents, nout, W.skip);

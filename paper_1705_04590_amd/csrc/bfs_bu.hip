@@ -75,7 +75,7 @@ __device__ __forceinline__ uint64_t stream_load(const uint64_t* p) { return __bu
 // here; a vertex that still needs its row is appended to the pending list
 // `pend` (vertex id, row position to resume at), and the sub-steps that
 // follow (k_bu_segment) scan those rows one column segment at a time.
-template <typename OffT, int HUB, int FILL, int SEG>
+template <typename OffT, int HUB, int FILL, int SEG, int BLK>
 __device__ __forceinline__ void bu_sweep_body(
     const int4* __restrict__ head, const uint64_t* __restrict__ iso, const uint32_t* __restrict__ nbase,
     const OffT* __restrict__ off, const int32_t* __restrict__ cols,
@@ -84,12 +84,14 @@ __device__ __forceinline__ void bu_sweep_body(
     int32_t* __restrict__ depth, int64_t W, int GW,
     int32_t next_depth, int serial_len, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot, int64_t n,
     int64_t src, uint64_t* __restrict__ pend) {
-    __shared__ int32_t s_list[BU_BLOCK / WAVE][BU_WIN];
-    __shared__ int32_t s_hidx[BU_BLOCK / WAVE][BU_WIN];
-    __shared__ unsigned long long s_nb[BU_BLOCK / WAVE][WAVE];
+    __shared__ int32_t s_list[BLK / WAVE][BU_WIN];
+    __shared__ int32_t s_hidx[BLK / WAVE][BU_WIN];
+    __shared__ unsigned long long s_nb[BLK / WAVE][WAVE];
     __shared__ uint64_t s_hb[HUB >= 2 ? HUB_BITS / 64 : 1];
+    // list index of each compacted row still to scan (window-relative)
+    __shared__ int16_t s_mx[BLK / WAVE][SEG || HUB == 3 ? 1 : BU_WIN];
     if (HUB >= 2) {
-        for (int i = threadIdx.x; i < HUB_BITS / 64; i += BU_BLOCK) s_hb[i] = hb[i];
+        for (int i = threadIdx.x; i < HUB_BITS / 64; i += BLK) s_hb[i] = hb[i];
         __syncthreads();
     }
     zero_slot(zslot);
@@ -99,7 +101,7 @@ __device__ __forceinline__ void bu_sweep_body(
     int32_t* hlist = s_hidx[wid];
     unsigned long long* nbw = s_nb[wid];
     const int64_t G = (W + GW - 1) / GW;
-    const int64_t nwaves = (int64_t)gridDim.x * (BU_BLOCK / WAVE);
+    const int64_t nwaves = (int64_t)gridDim.x * (BLK / WAVE);
     uint64_t my_n = 0, my_m = 0, my_x = 0;
     int64_t w0 = 0;
     // v found its parent at row position pos
@@ -113,7 +115,7 @@ __device__ __forceinline__ void bu_sweep_body(
         my_m += (uint64_t)deg;
         my_x += (uint64_t)(pos + 1);
     };
-    for (int64_t gi = (int64_t)blockIdx.x * (BU_BLOCK / WAVE) + wid; gi < G; gi += nwaves) {
+    for (int64_t gi = (int64_t)blockIdx.x * (BLK / WAVE) + wid; gi < G; gi += nwaves) {
         w0 = gi * GW;
         const int64_t w = w0 + lane;
         const bool mine = lane < GW && w < W;
@@ -141,6 +143,7 @@ __device__ __forceinline__ void bu_sweep_body(
                 }
             }
             wave_lds_sync();
+            int nmiss = 0;   // rows compacted for the second pass (wave-uniform)
             // heads of the first round; later rounds are prefetched one ahead
             int32_t v_next = lane < nw ? list[lane] : 0;
             int4 h_next = make_int4(0, -1, -1, -1);
@@ -173,28 +176,60 @@ __device__ __forceinline__ void bu_sweep_body(
                 // continuation: positions relative to the row start (rows hold < 2^31 entries);
                 // `pos` counts the head probes too when the head is not a row prefix
                 constexpr int32_t skip = HUB ? 0 : 3, pbase = HUB ? nprobe : 0;
-                int64_t beg = 0;
-                int32_t rp = deg;   // next entry to scan; deg when nothing is left
+                // the head did not settle v and its row goes on
+                const bool cont = HUB != 3 && act && par < 0 && deg > nprobe;
                 if (SEG) {
                     // the row goes to the pending list of the first sub-step
-                    const bool pnd = HUB != 3 && act && par < 0 && deg > nprobe;
-                    const uint64_t pm = __ballot(pnd);
+                    const uint64_t pm = __ballot(cont);
                     if (pm) {
                         const int leader = __ffsll((unsigned long long)pm) - 1;
                         uint64_t b = 0;
                         if (lane == leader)
                             b = atomicAdd((unsigned long long*)&slot[S_PEND0], (unsigned long long)__popcll(pm));
                         b = __shfl(b, leader, WAVE);
-                        if (pnd) pend[b + __popcll(pm & lanemask_lt())] = (uint64_t)(uint32_t)v | ((uint64_t)skip << 32);
+                        if (cont) pend[b + __popcll(pm & lanemask_lt())] = (uint64_t)(uint32_t)v | ((uint64_t)skip << 32);
                     }
-                    if (pnd) my_x += (uint64_t)(HUB ? nprobe : 3);   // the head; the sub-steps count the rest
+                    if (cont) my_x += (uint64_t)(HUB ? nprobe : 3);   // the head; the sub-steps count the rest
                     else if (par >= 0) found(v, par, pos, deg);
                     else if (act) my_x += (uint64_t)(deg > nprobe ? pbase + deg : deg);
                     if (FILL && act) hlist[r + lane] = par;
                     continue;
                 }
-                if (HUB != 3 && par < 0 && deg > nprobe) {
+                // rows to scan are compacted to the front of the list (slots
+                // whose vertices were already loaded) and scanned after the
+                // window's heads, 64 at a time: a round of heads no longer
+                // waits for the one lane whose row needs a chain of loads
+                const uint64_t cm = __ballot(cont);
+                if (cont) {
+                    const int k = nmiss + __popcll(cm & lanemask_lt());
+                    list[k] = v;
+                    s_mx[wid][k] = (int16_t)(r + lane);
+                }
+                nmiss += __popcll(cm);
+                if (!cont) {
+                    if (par >= 0) found(v, par, pos, deg);
+                    else if (act) my_x += (uint64_t)(deg > nprobe ? pbase + deg : deg);
+                    // the entry's result replaces its head index (read one round ago)
+                    if (FILL && act) hlist[r + lane] = par;
+                }
+            }
+            wave_lds_sync();
+            for (int r = 0; r < nmiss; r += WAVE) {
+                constexpr int32_t nprobe = HUB >= 2 ? 2 : 3;
+                constexpr int32_t skip = HUB ? 0 : 3, pbase = HUB ? nprobe : 0;
+                const bool act = r + lane < nmiss;
+                const int32_t v = act ? list[r + lane] : 0;
+                const int idx = act ? (int)s_mx[wid][r + lane] : 0;
+                int64_t beg = 0;
+                int32_t deg = 0;
+                if (act) {
                     beg = (int64_t)off[v];
+                    deg = (int32_t)((int64_t)off[v + 1] - beg);
+                }
+                int32_t par = -1;
+                int32_t pos = 0;   // position of the hit in the row
+                int32_t rp = deg;   // next entry to scan; deg when nothing is left
+                if (act) {
                     const int32_t lim = deg - skip > serial_len ? skip + serial_len : deg;
                     const int32_t* row = cols + beg;
                     for (rp = skip; rp < lim; rp += 4) {
@@ -215,7 +250,7 @@ __device__ __forceinline__ void bu_sweep_body(
                     if (par >= 0) pos = pbase + rp;
                     else if (rp > lim) rp = lim;
                 }
-                uint64_t rem = HUB == 3 ? 0ull : __ballot(par < 0 && rp < deg);
+                uint64_t rem = __ballot(act && par < 0 && rp < deg);
                 while (rem) {
                     const int l = __ffsll((unsigned long long)rem) - 1;
                     rem &= rem - 1;
@@ -245,9 +280,8 @@ __device__ __forceinline__ void bu_sweep_body(
                     }
                 }
                 if (par >= 0) found(v, par, pos, deg);
-                else if (act) my_x += (uint64_t)(deg > nprobe ? pbase + deg : deg);
-                // the entry's result replaces its head index (read one round ago)
-                if (FILL && act) hlist[r + lane] = par;
+                else if (act) my_x += (uint64_t)(pbase + deg);
+                if (FILL && act) hlist[idx] = par;
             }
             wave_lds_sync();
         }
@@ -294,7 +328,7 @@ __device__ __forceinline__ void bu_sweep_body(
         wave_lds_sync();
     }
     uint64_t* ln = slot_line(slot);
-    block_add3<BU_BLOCK / WAVE>(my_n, my_m, my_x, &ln[S_NNEXT], &ln[S_MNEXT], &ln[S_EXAMINED]);
+    block_add3<BLK / WAVE>(my_n, my_m, my_x, &ln[S_NNEXT], &ln[S_MNEXT], &ln[S_EXAMINED]);
 }
 
 #define BFS_SWEEP_PARAMS                                                                                          \
@@ -309,16 +343,17 @@ __device__ __forceinline__ void bu_sweep_body(
         slot, zslot, n, src, pend
 
 // the bottom-up step
-template <typename OffT, int HUB, int FILL, int SEG>
-__global__ __launch_bounds__(BU_BLOCK, 5) void k_bu_sweep(BFS_SWEEP_PARAMS) {
-    bu_sweep_body<OffT, HUB, FILL, SEG>(BFS_SWEEP_ARGS);
+// (BLK threads per workgroup, one 64-lane wave per group of words)
+template <typename OffT, int HUB, int FILL, int SEG, int BLK>
+__global__ __launch_bounds__(BLK, 5) void k_bu_sweep(BFS_SWEEP_PARAMS) {
+    bu_sweep_body<OffT, HUB, FILL, SEG, BLK>(BFS_SWEEP_ARGS);
 }
 
 // the hub pre-pass of a heavy top-down level (a kernel of its own name, so
 // profiles keep it apart from the bottom-up step)
 template <typename OffT, int FILL>
 __global__ __launch_bounds__(BU_BLOCK) void k_td_hub_prepass(BFS_SWEEP_PARAMS) {
-    bu_sweep_body<OffT, 3, FILL, 0>(BFS_SWEEP_ARGS);
+    bu_sweep_body<OffT, 3, FILL, 0, BU_BLOCK>(BFS_SWEEP_ARGS);
 }
 
 // ------------------------------------------------------------ column segments
@@ -473,33 +508,41 @@ void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t*
                      const OffT* off, const int32_t* cols, const uint64_t* fbits, const uint64_t* hb, uint64_t* nbits,
                      uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W,
                      int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot, bool fill, int64_t n,
-                     int64_t src, uint64_t* pend) {
-    int gw = group_words(W, L.grid_cap * (BU_BLOCK / WAVE));
+                     int64_t src, uint64_t* pend, int block, int group_cap) {
+    // the column-blocked sweep and the pre-pass keep the default shape
+    const int blk = (hub == 3 || pend || (block != 128 && block != 512)) ? BU_BLOCK : block;
+    int gw = group_words(W, L.grid_cap * (blk / WAVE));
+    if (group_cap > 0 && gw > group_cap) gw = group_cap;
     if (fill && gw > FILL_GW) gw = FILL_GW;
     const int64_t G = (W + gw - 1) / gw;
-    const int g = grid_for(G, BU_BLOCK / WAVE, L.grid_cap);
-#define BFS_SWEEP(H, F, S)                                                                                       \
-    hipLaunchKernelGGL((k_bu_sweep<OffT, H, F, S>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off,  \
+    const int g = grid_for(G, blk / WAVE, L.grid_cap);
+#define BFS_SWEEP(H, F, S, B)                                                                                     \
+    hipLaunchKernelGGL((k_bu_sweep<OffT, H, F, S, B>), dim3(g), dim3(B), 0, L.stream, head, iso, nbase, off,       \
                        cols, fbits, hb, nbits, visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot,  \
                        zslot, n, src, pend)
 #define BFS_PREPASS(F)                                                                                              \
     hipLaunchKernelGGL((k_td_hub_prepass<OffT, F>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off,    \
                        cols, fbits, hb, nbits, visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot,     \
                        zslot, n, src, pend)
-#define BFS_SWEEP_H(F, S)                 \
-    if (hub == 2) BFS_SWEEP(2, F, S);     \
-    else if (hub == 1) BFS_SWEEP(1, F, S); \
-    else BFS_SWEEP(0, F, S);
+#define BFS_SWEEP_H(F, S, B)                 \
+    if (hub == 2) BFS_SWEEP(2, F, S, B);     \
+    else if (hub == 1) BFS_SWEEP(1, F, S, B); \
+    else BFS_SWEEP(0, F, S, B);
+#define BFS_SWEEP_HB(F)                                   \
+    if (blk == 128) { BFS_SWEEP_H(F, 0, 128) }            \
+    else if (blk == 512) { BFS_SWEEP_H(F, 0, 512) }       \
+    else { BFS_SWEEP_H(F, 0, BU_BLOCK) }
     if (hub == 3) {
         if (fill) BFS_PREPASS(1);
         else BFS_PREPASS(0);
     } else if (pend) {
-        if (fill) { BFS_SWEEP_H(1, 1) }
-        else { BFS_SWEEP_H(0, 1) }
+        if (fill) { BFS_SWEEP_H(1, 1, BU_BLOCK) }
+        else { BFS_SWEEP_H(0, 1, BU_BLOCK) }
     } else {
-        if (fill) { BFS_SWEEP_H(1, 0) }
-        else { BFS_SWEEP_H(0, 0) }
+        if (fill) { BFS_SWEEP_HB(1) }
+        else { BFS_SWEEP_HB(0) }
     }
+#undef BFS_SWEEP_HB
 #undef BFS_SWEEP_H
 #undef BFS_SWEEP
 #undef BFS_PREPASS
@@ -717,7 +760,7 @@ void launch_hub_gather(const Launch& L, const uint64_t* fbits, const int32_t* hu
     template void launch_bu_sweep<T>(const Launch&, const int4*, int, const uint64_t*, const uint32_t*,          \
                                      const T*, const int32_t*, const uint64_t*, const uint64_t*, uint64_t*,      \
                                      uint64_t*, uint64_t*, int32_t*, int32_t*, int64_t, int32_t, int, uint64_t*, \
-                                     uint64_t*, bool, int64_t, int64_t, uint64_t*);                              \
+                                     uint64_t*, bool, int64_t, int64_t, uint64_t*, int, int);                    \
     template void launch_bu_segment<T>(const Launch&, const T*, const int32_t*, const uint64_t*, const uint64_t*, \
                                        const uint64_t*, uint64_t*, uint64_t*, int64_t, int32_t*, int32_t*,       \
                                        uint64_t*, uint64_t*, uint64_t*, int32_t, int, uint64_t*);                \

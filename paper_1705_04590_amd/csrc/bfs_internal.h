@@ -38,12 +38,23 @@ constexpr int BU_BLOCK = 256;                 // 4 waves, one 64-vertex word per
 enum { S_QLEN = 0, S_NNEXT = 1, S_MNEXT = 2, S_EXAMINED = 3, S_DISTINCT = 5, S_PEND0 = 6, S_MDISTINCT = 15,
        SLOT_LINE = 16, SLOT_SPREAD = 16, SLOT_WORDS = SLOT_LINE * SLOT_SPREAD, SLOTS = 3 };
 constexpr int BU_MAX_SEGMENTS = 8;
+// top-down column segments: at most this many, by default on levels of at
+// least this many frontier edges
+constexpr int TD_MAX_SEGMENTS = 8;
+constexpr int64_t TD_SEG_MIN_EDGES = (int64_t)1 << 20;
 static_assert(S_PEND0 + BU_MAX_SEGMENTS < S_MDISTINCT, "pending counts must fit line 0 of a slot");
 
 // sum of word `w` over the lines of a slot copied to the host
 inline uint64_t slot_sum(const uint64_t* h, int w) {
     uint64_t s = 0;
     for (int j = 0; j < SLOT_SPREAD; ++j) s += h[j * SLOT_LINE + w];
+    return s;
+}
+
+// maximum of word `w` over the lines of a slot copied to the host
+inline uint64_t slot_max(const uint64_t* h, int w) {
+    uint64_t s = 0;
+    for (int j = 0; j < SLOT_SPREAD; ++j) s = h[j * SLOT_LINE + w] > s ? h[j * SLOT_LINE + w] : s;
     return s;
 }
 
@@ -82,12 +93,24 @@ template <typename OffT>
 int launch_td_scan(const Launch& L, const OffT* off, const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host,
                    int64_t* scan, int32_t* tile_start, int64_t* partial, int64_t* total_out);
 
+// total_dev (may be NULL): the edge count on the device (total then bounds
+// the grid); segpos (may be NULL): per queue entry, the row position where
+// its edges start (a column segment's first entry); block: threads per
+// workgroup (128, 512; anything else = TD_BLOCK), the tile stays TD_TILE edges
 template <typename OffT>
 void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t* cols, int64_t nnz,
                       const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host, const int64_t* scan,
                       const int32_t* tile_start, int64_t total, int32_t* parent, int32_t* depth,
                       uint64_t* visited, uint64_t* claim, int32_t* qnext, uint64_t* slot, uint64_t* zslot,
-                      int32_t next_depth);
+                      int32_t next_depth, const int64_t* total_dev = nullptr, const int32_t* segpos = nullptr,
+                      int block = 0);
+// the degree scan of one column segment: each queue entry's entries with ids
+// in [lo, hi) (its sorted row's sub-range, found by binary search); their
+// start positions go to segpos, the segment's edge total to *total_out
+template <typename OffT>
+int launch_td_scan_seg(const Launch& L, const OffT* off, const int32_t* cols, const int32_t* q,
+                       const uint64_t* qlen_dev, int64_t qlen_host, int64_t lo, int64_t hi, int64_t* scan,
+                       int32_t* tile_start, int64_t* partial, int32_t* segpos, int64_t* total_out);
 
 // head kinds (hub): 0 row heads, 1 hub heads, 2 hub heads with hub ranks
 // (then hb holds the hubs' frontier bits, HUB_BITS bits), 3 the same probes
@@ -95,13 +118,15 @@ void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t*
 // were not initialised; the sweep also writes -1 to every entry of the
 // unreached and isolated vertices (the source, of id src, excepted)
 // pend (may be NULL): column-blocked level; rows that need scanning past
-// their head are appended to pend (count in slot[S_PEND0]) for the sub-steps
+// their head are appended to pend (count in slot[S_PEND0]) for the sub-steps.
+// block: threads per workgroup (128, 512; anything else = BU_BLOCK);
+// group_cap > 0 caps the 64-vertex words per wave's work unit
 template <typename OffT>
 void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t* iso, const uint32_t* nbase,
                      const OffT* off, const int32_t* cols, const uint64_t* fbits, const uint64_t* hb, uint64_t* nbits,
                      uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W,
                      int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot, bool fill, int64_t n,
-                     int64_t src, uint64_t* pend = nullptr);
+                     int64_t src, uint64_t* pend = nullptr, int block = 0, int group_cap = 0);
 // one column-segment sub-step: pending rows (count *cin) scanned over their
 // entries < seg_end; rows that reach a later segment go to pout (count *cout)
 template <typename OffT>
@@ -185,7 +210,7 @@ void launch_merge_exact(const Launch& L, const OffT* off, const uint64_t* visite
 // NNEXT, MNEXT, MFULL and EXAM are spread over the slot's lines; QLEN, OR and
 // CONV live in line 0.
 enum { M_SLOT_QLEN = 0, M_SLOT_NNEXT = 1, M_SLOT_MNEXT = 2, M_SLOT_OR = 3, M_SLOT_MFULL = 4, M_SLOT_EXAM = 5,
-       M_SLOT_CONV = 6 };
+       M_SLOT_CONV = 6, M_SLOT_MAXDEG = 8 };
 
 template <typename OffT>
 void launch_ms_init(const Launch& L, const OffT* off, int64_t n, int k, const int64_t* src, const uint64_t* iso,
@@ -201,14 +226,22 @@ void launch_ms_bu(const Launch& L, const OffT* off, const int32_t* cols, int64_t
                   uint64_t* visited, uint64_t full, const uint64_t* active_dev, int32_t* par_vm, uint16_t* lvl_vm,
                   uint16_t level, int serial, uint64_t* slot, uint64_t* zslot);
 void launch_ms_mask_to_queue(const Launch& L, const uint64_t* N, int64_t n, int32_t* q, uint64_t* qlen);
+// The persistent multi-source engine takes a level only while no frontier
+// row is longer than MS_ENGINE_MAX_DEG (a workgroup expands whole rows of its
+// queue chunk), and while the rows' lengths are not known only up to
+// MS_ENGINE_FIRST_CAP frontier edges.
+constexpr int64_t MS_ENGINE_MAX_DEG = 4096;
+constexpr int64_t MS_ENGINE_FIRST_CAP = 65536;
 // persistent multi-source top-down engine: inputs, and the state it leaves
 struct MsIn {
     int64_t qlen, n_f, m_f, m_u, level;
+    int64_t maxdeg;    // longest row in the frontier, -1 when not known
 };
 struct MsState {
     int64_t qlen, n_f, m_f, m_u, level;
     int64_t levels_done, reason, reached, examined;
     int64_t swapped;   // 1: the frontier masks are now in the array passed as N (and F is clear)
+    int64_t maxdeg;    // longest row in the frontier it leaves (-1 when not known)
 };
 template <typename OffT>
 int ms_persist_max_groups();

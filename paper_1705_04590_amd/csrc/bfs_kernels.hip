@@ -189,15 +189,64 @@ int launch_td_scan(const Launch& L, const OffT* off, const int32_t* q, const uin
     return 3;
 }
 
+// ------------------------------------------------------------------ column segments
+// first position p in the sorted row cols[b, e) with cols[p] >= x (e when none)
+__device__ __forceinline__ int64_t row_lower_bound(const int32_t* __restrict__ cols, int64_t b, int64_t e, int64_t x) {
+    while (b < e) {
+        const int64_t mid = (b + e) >> 1;
+        if ((int64_t)cols[mid] < x) b = mid + 1; else e = mid;
+    }
+    return b;
+}
+
+// queue entry i's entries with ids in [lo, hi): their count, kept in `keep`,
+// and the position of the first of them in the row, in `segpos`
+template <typename OffT>
+struct QueueSegDegree {
+    const OffT* off;
+    const int32_t* cols;
+    const int32_t* q;
+    int64_t lo, hi;
+    int64_t* keep;
+    int32_t* segpos;
+    __device__ int64_t operator()(int64_t i) const {
+        const int32_t u = q[i];
+        const int64_t b = (int64_t)off[u], e = (int64_t)off[u + 1];
+        const int64_t p0 = lo > 0 ? row_lower_bound(cols, b, e, lo) : b;
+        const int64_t p1 = row_lower_bound(cols, p0, e, hi);
+        segpos[i] = (int32_t)(p0 - b);
+        keep[i] = p1 - p0;
+        return p1 - p0;
+    }
+};
+
+template <typename OffT>
+int launch_td_scan_seg(const Launch& L, const OffT* off, const int32_t* cols, const int32_t* q,
+                       const uint64_t* qlen_dev, int64_t qlen_host, int64_t lo, int64_t hi, int64_t* scan,
+                       int32_t* tile_start, int64_t* partial, int32_t* segpos, int64_t* total_out) {
+    const QueueSegDegree<OffT> val{off, cols, q, lo, hi, scan, segpos};
+    const int64_t nb = (qlen_host + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb <= 1)
+        return launch_scan(L.stream, val, qlen_dev, qlen_host, partial, TileSink{scan, tile_start, total_out});
+    hipLaunchKernelGGL((k_scan_partials_g<QueueSegDegree<OffT>>), dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, L.stream,
+                       val, qlen_dev, qlen_host, partial);
+    hipLaunchKernelGGL(k_scan_top_g<0>, dim3(1), dim3(SCAN_BLOCK), 0, L.stream, partial, nb);
+    hipLaunchKernelGGL((k_scan_apply_g<KeptValue, TileSink>), dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, L.stream,
+                       KeptValue{scan}, qlen_dev, qlen_host, partial, nb, TileSink{scan, tile_start, total_out});
+    return 3;
+}
+
 // ------------------------------------------------------------------ top-down expand
-template <typename OffT, int MODE>
-__global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
+// BLK threads per workgroup; a tile keeps TD_TILE edges, TD_TILE / BLK per thread
+template <typename OffT, int MODE, int BLK>
+__global__ __launch_bounds__(BLK) void k_td_expand(
     const OffT* __restrict__ off, const int32_t* __restrict__ cols, const int32_t* __restrict__ q,
     const uint64_t* __restrict__ qlen_dev, int64_t qlen_host, const int64_t* __restrict__ scan,
     const int32_t* __restrict__ tile_start, const int64_t* __restrict__ total_dev, int64_t total_host, int64_t nnz,
     int32_t* __restrict__ parent, int32_t* __restrict__ depth, uint64_t* __restrict__ visited,
     uint64_t* __restrict__ claim, int32_t* __restrict__ qnext, uint64_t* __restrict__ slot,
-    uint64_t* __restrict__ zslot, int32_t next_depth) {
+    uint64_t* __restrict__ zslot, int32_t next_depth, const int32_t* __restrict__ segpos) {
+    constexpr int EPT = TD_TILE / BLK;
     __shared__ int32_t s_start[TD_TILE + 1];   // first edge of staged vertex j, relative to the tile
     __shared__ int64_t s_base[TD_TILE + 1];    // off[u_j] - scan[j]: cols index = s_base[j] + edge index
     __shared__ int32_t s_u[TD_TILE + 1];
@@ -219,39 +268,59 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
         const int64_t e1 = (e0 + TD_TILE < total) ? e0 + TD_TILE : total;
         const int i0 = tile_start[t];
         int nv = tile_start[t + 1] - i0 + 1;
-        // every queued vertex has an out-edge, so a tile spans at most
-        // TD_TILE + 1 of them; the clamps only guard memory
-        if (nv > TD_TILE + 1) nv = TD_TILE + 1;
         if (i0 < 0 || i0 >= qlen) nv = 0;
         else if (nv > qlen - i0) nv = (int)(qlen - i0);
-        for (int j = threadIdx.x; j < nv; j += TD_BLOCK) {
+        // a tile spans at most TD_TILE + 1 entries when every entry has
+        // edges; a column segment leaves entries with none in it between the
+        // tile's owners, and a tile spanning more than LDS holds finds each
+        // edge's entry by binary search in the global scan instead
+        const bool staged = nv <= TD_TILE + 1;
+        const int ns = staged ? nv : 0;
+        for (int j = threadIdx.x; j < ns; j += BLK) {
             int32_t u = q[i0 + j];
             int64_t sc = scan[i0 + j];
             int64_t rel = sc - e0;
             s_start[j] = rel < 0 ? 0 : (int32_t)rel;
-            s_base[j] = (int64_t)off[u] - sc;
+            // column segment: the row's entries from segpos (its first
+            // entry inside the segment) on
+            s_base[j] = (int64_t)off[u] + (segpos ? (int64_t)segpos[i0 + j] : 0) - sc;
             s_u[j] = u;
         }
         __syncthreads();
-        // the thread's TD_EPT edges move through each stage together so their
+        // the thread's EPT edges move through each stage together so their
         // loads and atomics are in flight at the same time
-        int32_t vv[TD_EPT], uu[TD_EPT];
-        bool cand[TD_EPT];
+        int32_t vv[EPT], uu[EPT];
+        bool cand[EPT];
 #pragma unroll
-        for (int k = 0; k < TD_EPT; ++k) {
-            const int p = k * TD_BLOCK + threadIdx.x;
+        for (int k = 0; k < EPT; ++k) {
+            const int p = k * BLK + threadIdx.x;
             const int64_t e = e0 + p;
             cand[k] = e < e1 && nv > 0;
             vv[k] = 0;
             uu[k] = 0;
             if (cand[k]) {
-                int lo = 0, hi = nv - 1;   // last staged vertex starting at or before p
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (s_start[mid] <= p) lo = mid; else hi = mid - 1;
+                int64_t pos;
+                if (staged) {
+                    int lo = 0, hi = nv - 1;   // last staged vertex starting at or before p
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (s_start[mid] <= p) lo = mid; else hi = mid - 1;
+                    }
+                    uu[k] = s_u[lo];
+                    pos = s_base[lo] + e;
+                } else {
+                    // last entry whose edges start at or before e (entries
+                    // without edges share their successor's start, so the
+                    // last one with that start is the owner)
+                    int64_t lo = i0, hi = i0 + nv - 1;
+                    while (lo < hi) {
+                        const int64_t mid = (lo + hi + 1) >> 1;
+                        if (scan[mid] <= e) lo = mid; else hi = mid - 1;
+                    }
+                    const int32_t u = q[lo];
+                    uu[k] = u;
+                    pos = (int64_t)off[u] + (segpos ? (int64_t)segpos[lo] : 0) + (e - scan[lo]);
                 }
-                uu[k] = s_u[lo];
-                int64_t pos = s_base[lo] + e;
                 if (pos < 0 || pos >= nnz) pos = 0;   // unreachable for a consistent scan
                 vv[k] = cols[pos];
             }
@@ -259,12 +328,12 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
         // one probe of the visited bitmap per edge; ANY modes claim on that
         // same bitmap, MIN mode keeps it frozen for the level and claims on
         // a separate bitmap (all frontier neighbours must reach atomicMin)
-        uint64_t vw[TD_EPT];
+        uint64_t vw[EPT];
 #pragma unroll
-        for (int k = 0; k < TD_EPT; ++k) vw[k] = cand[k] ? visited[vv[k] >> 6] : ~0ull;
-        bool won[TD_EPT];
+        for (int k = 0; k < EPT; ++k) vw[k] = cand[k] ? visited[vv[k] >> 6] : ~0ull;
+        bool won[EPT];
 #pragma unroll
-        for (int k = 0; k < TD_EPT; ++k) {
+        for (int k = 0; k < EPT; ++k) {
             const int32_t v = vv[k];
             const uint64_t bit = 1ull << (v & 63);
             won[k] = false;
@@ -293,7 +362,7 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
             }
         }
 #pragma unroll
-        for (int k = 0; k < TD_EPT; ++k) {
+        for (int k = 0; k < EPT; ++k) {
             const int32_t v = vv[k];
             int64_t dv = 0;
             if (won[k]) {
@@ -322,14 +391,14 @@ __global__ __launch_bounds__(TD_BLOCK) void k_td_expand(
             if (threadIdx.x == 0 && cnt > 0)
                 s_qbase = atomicAdd((unsigned long long*)&slot[S_QLEN], (unsigned long long)cnt);
             __syncthreads();
-            for (int j = threadIdx.x; j < cnt; j += TD_BLOCK) qnext[s_qbase + j] = s_out[j];
+            for (int j = threadIdx.x; j < cnt; j += BLK) qnext[s_qbase + j] = s_out[j];
             __syncthreads();
             if (threadIdx.x == 0) s_cnt = 0;
         }
         __syncthreads();
     }
     uint64_t* ln = slot_line(slot);
-    block_add3<TD_BLOCK / WAVE>(my_n, my_m, 0, &ln[S_NNEXT], &ln[S_MNEXT], nullptr);
+    block_add3<BLK / WAVE>(my_n, my_m, 0, &ln[S_NNEXT], &ln[S_MNEXT], nullptr);
 }
 
 template <typename OffT>
@@ -337,18 +406,26 @@ void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t*
                       const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host, const int64_t* scan,
                       const int32_t* tile_start, int64_t total, int32_t* parent, int32_t* depth,
                       uint64_t* visited, uint64_t* claim, int32_t* qnext, uint64_t* slot, uint64_t* zslot,
-                      int32_t next_depth) {
+                      int32_t next_depth, const int64_t* total_dev, const int32_t* segpos, int block) {
+    // with total_dev the edge count is read on the device and `total` only
+    // bounds the grid
     const int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
     const int g = grid_for(ntiles, 1, L.grid_cap);
-    const int64_t* total_dev = nullptr;
-#define BFS_EXPAND(M)                                                                                        \
-    hipLaunchKernelGGL((k_td_expand<OffT, M>), dim3(g), dim3(TD_BLOCK), 0, L.stream, off, cols, q, qlen_dev, \
-                       qlen_host, scan, tile_start, total_dev, total, nnz, parent, depth, visited, claim,      \
-                       qnext, slot, zslot, next_depth)
-    if (mode == CLAIM_MIN) BFS_EXPAND(CLAIM_MIN);
-    else if (mode == CLAIM_CAS) BFS_EXPAND(CLAIM_CAS);
-    else if (mode == CLAIM_BENIGN) BFS_EXPAND(CLAIM_BENIGN);
-    else BFS_EXPAND(CLAIM_BITMAP);
+#define BFS_EXPAND(M, B)                                                                                 \
+    hipLaunchKernelGGL((k_td_expand<OffT, M, B>), dim3(g), dim3(B), 0, L.stream, off, cols, q, qlen_dev, \
+                       qlen_host, scan, tile_start, total_dev, total, nnz, parent, depth, visited, claim,  \
+                       qnext, slot, zslot, next_depth, segpos)
+#define BFS_EXPAND_B(M)                          \
+    do {                                         \
+        if (block == 128) BFS_EXPAND(M, 128);    \
+        else if (block == 512) BFS_EXPAND(M, 512); \
+        else BFS_EXPAND(M, TD_BLOCK);            \
+    } while (0)
+    if (mode == CLAIM_MIN) BFS_EXPAND_B(CLAIM_MIN);
+    else if (mode == CLAIM_CAS) BFS_EXPAND_B(CLAIM_CAS);
+    else if (mode == CLAIM_BENIGN) BFS_EXPAND_B(CLAIM_BENIGN);
+    else BFS_EXPAND_B(CLAIM_BITMAP);
+#undef BFS_EXPAND_B
 #undef BFS_EXPAND
 }
 
@@ -516,7 +593,10 @@ void launch_validate_csr(const Launch& L, const OffT* off, const int32_t* cols, 
     template void launch_td_expand<T>(const Launch&, int, const T*, const int32_t*, int64_t, const int32_t*,   \
                                       const uint64_t*, int64_t, const int64_t*, const int32_t*, int64_t,        \
                                       int32_t*, int32_t*, uint64_t*, uint64_t*, int32_t*, uint64_t*,            \
-                                      uint64_t*, int32_t);                                                      \
+                                      uint64_t*, int32_t, const int64_t*, const int32_t*, int);                 \
+    template int launch_td_scan_seg<T>(const Launch&, const T*, const int32_t*, const int32_t*, const uint64_t*, \
+                                       int64_t, int64_t, int64_t, int64_t*, int32_t*, int64_t*, int32_t*,        \
+                                       int64_t*);                                                                 \
     template void launch_validate_csr<T>(const Launch&, const T*, const int32_t*, int64_t, int64_t, uint32_t,  \
                                          uint32_t*);                                                              \
     template void launch_merge_exact<T>(const Launch&, const T*, const uint64_t*, uint64_t*, uint64_t*, int64_t, \

@@ -23,32 +23,58 @@
 namespace bfsk {
 
 // counter slot words of a multi-source level
-enum { M_QLEN = 0, M_NNEXT = 1, M_MNEXT = 2, M_OR = 3, M_MFULL = 4, M_EXAM = 5, M_HUBS = 7 };
+enum { M_QLEN = 0, M_NNEXT = 1, M_MNEXT = 2, M_OR = 3, M_MFULL = 4, M_EXAM = 5, M_HUBS = 7, M_MAXDEG = 8 };
+
 
 // rows longer than this are not scanned by the resolve pass: their parents
 // come from the frontier side instead (k_ms_hub_resolve)
 constexpr int64_t MS_HUB_ROW = 512;
 
+// Workgroup totals added once per workgroup to its line of the slot (sums;
+// the OR of the new-source bits; the maximum row length `mx`).  Every word is
+// spread over the SLOT_SPREAD lines, so no single address takes an atomic
+// from each of thousands of workgroups; readers combine the lines
+// (dslot_or / dslot_max / sums).
 __device__ __forceinline__ void or_reduce_add(uint64_t n, uint64_t m, uint64_t orv, uint64_t mfull, uint64_t exam,
-                                              uint64_t* slot) {
-    __shared__ uint64_t red[5][4];
+                                              uint64_t* slot, uint64_t mx = 0) {
+    __shared__ uint64_t red[6][4];
     n = wave_sum(n); m = wave_sum(m); mfull = wave_sum(mfull); exam = wave_sum(exam);
-    for (int d = 32; d >= 1; d >>= 1) orv |= __shfl_xor(orv, d, WAVE);
+    for (int d = 32; d >= 1; d >>= 1) {
+        orv |= __shfl_xor(orv, d, WAVE);
+        mx = max(mx, (uint64_t)__shfl_xor(mx, d, WAVE));
+    }
     const int wid = threadIdx.x / WAVE;
-    if (lane_id() == 0) { red[0][wid] = n; red[1][wid] = m; red[2][wid] = orv; red[3][wid] = mfull; red[4][wid] = exam; }
+    if (lane_id() == 0) {
+        red[0][wid] = n; red[1][wid] = m; red[2][wid] = orv; red[3][wid] = mfull; red[4][wid] = exam;
+        red[5][wid] = mx;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint64_t a = 0, b = 0, c = 0, e = 0, x = 0;
+        uint64_t a = 0, b = 0, c = 0, e = 0, x = 0, y = 0;
         for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) {
             a += red[0][i]; b += red[1][i]; c |= red[2][i]; e += red[3][i]; x += red[4][i];
+            y = max(y, red[5][i]);
         }
         uint64_t* ln = slot_line(slot);
         if (a) atomicAdd((unsigned long long*)&ln[M_NNEXT], (unsigned long long)a);
         if (b) atomicAdd((unsigned long long*)&ln[M_MNEXT], (unsigned long long)b);
-        if (c) atomicOr((unsigned long long*)&slot[M_OR], (unsigned long long)c);
+        if (c) atomicOr((unsigned long long*)&ln[M_OR], (unsigned long long)c);
         if (e) atomicAdd((unsigned long long*)&ln[M_MFULL], (unsigned long long)e);
         if (x) atomicAdd((unsigned long long*)&ln[M_EXAM], (unsigned long long)x);
+        if (y) atomicMax((unsigned long long*)&ln[M_MAXDEG], (unsigned long long)y);
     }
+}
+
+// OR / maximum of word w over the lines of a slot
+__device__ __forceinline__ uint64_t dslot_or(const uint64_t* slot, int w) {
+    uint64_t r = 0;
+    for (int j = 0; j < SLOT_SPREAD; ++j) r |= ld_dev(&slot[j * SLOT_LINE + w]);
+    return r;
+}
+__device__ __forceinline__ uint64_t dslot_max(const uint64_t* slot, int w) {
+    uint64_t r = 0;
+    for (int j = 0; j < SLOT_SPREAD; ++j) r = max(r, ld_dev(&slot[j * SLOT_LINE + w]));
+    return r;
 }
 
 __device__ __forceinline__ void record(int32_t* __restrict__ par_vm, uint16_t* __restrict__ lvl_vm, int64_t v,
@@ -295,7 +321,7 @@ __global__ __launch_bounds__(256) void k_ms_resolve(const OffT* __restrict__ off
                                                     uint64_t* __restrict__ slot) {
     const int64_t qlen = (int64_t)*qlen_dev;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    uint64_t cn = 0, cm = 0, cor = 0, cfull = 0, cx = 0;
+    uint64_t cn = 0, cm = 0, cor = 0, cfull = 0, cx = 0, cmax = 0;
     for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < qlen; i0 += stride) {
         const int64_t i = i0 + threadIdx.x;
         int64_t v = 0, beg = 0, end = 0;
@@ -332,9 +358,11 @@ __global__ __launch_bounds__(256) void k_ms_resolve(const OffT* __restrict__ off
             cor |= need;
             cx += (uint64_t)ex;
             if (vis == full) cfull += (uint64_t)(end - beg);
+            cmax = max(cmax, (uint64_t)(end - beg));
         }
     }
-    or_reduce_add(cn, cm, cor, cfull, cx, slot);
+    // with the longest row of the new frontier (the persistent engine's guard)
+    or_reduce_add(cn, cm, cor, cfull, cx, slot, cmax);
 }
 
 // ---------------------------------------------------------------- bottom-up
@@ -347,7 +375,7 @@ __global__ __launch_bounds__(256) void k_ms_bu_sweep(const OffT* __restrict__ of
                                                      uint16_t level, int serial, uint64_t* __restrict__ slot,
                                                      uint64_t* __restrict__ zslot) {
     zero_slot(zslot);
-    const uint64_t active = *active_dev;
+    const uint64_t active = dslot_or(active_dev, 0);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     uint64_t cn = 0, cm = 0, cor = 0, cfull = 0, cx = 0;
     for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n; v0 += stride) {
@@ -564,6 +592,7 @@ __global__ __launch_bounds__(MP_BLOCK) void k_ms_persist(
     int32_t *qcur = qa, *qnext = qb;
     int64_t done = 0, reason = ENG_EMPTY, reached = 0, examined = 0;
     uint64_t last_or = 0;
+    int64_t maxdeg = in.maxdeg;   // longest row of the current frontier, -1 when not known
     uint32_t nbar = 0;
     bool fail = false;
 
@@ -614,7 +643,10 @@ __global__ __launch_bounds__(MP_BLOCK) void k_ms_persist(
     for (;;) {
         if (done >= max_levels) { reason = ENG_LEVEL_CAP; break; }
         if (done > 0 && (double)m_f * alpha > (double)m_u) { reason = ENG_TO_BU; break; }
-        if (m_f > edge_cap) { reason = ENG_EDGE_CAP; break; }
+        if (m_f > (maxdeg < 0 ? min(edge_cap, MS_ENGINE_FIRST_CAP) : edge_cap) || maxdeg > MS_ENGINE_MAX_DEG) {
+            reason = ENG_EDGE_CAP;
+            break;
+        }
         uint64_t* slot = ctr + (size_t)(done % SLOTS) * SLOT_WORDS;
         const uint16_t next_level = (uint16_t)(level + 1);
         const int64_t C = (qlen + G - 1) / G;
@@ -652,7 +684,7 @@ __global__ __launch_bounds__(MP_BLOCK) void k_ms_persist(
         const int64_t nq = (int64_t)ld_dev(&slot[M_QLEN]);
         const int64_t Cq = (nq + G - 1) / G;
         const int64_t r_beg = min(nq, (int64_t)g * Cq), r_end = min(nq, r_beg + Cq);
-        uint64_t cn = 0, cm = 0, cor = 0, cfull = 0, cx = 0;
+        uint64_t cn = 0, cm = 0, cor = 0, cfull = 0, cx = 0, cmax = 0;
         for (int64_t c0 = r_beg; c0 < r_end; c0 += MP_BLOCK) {
             const int64_t i = c0 + tid;
             int64_t v = 0, beg = 0, end = 0;
@@ -686,9 +718,10 @@ __global__ __launch_bounds__(MP_BLOCK) void k_ms_persist(
                 cor |= need;
                 cx += (uint64_t)ex;
                 if (vis == full) cfull += (uint64_t)(end - beg);
+                cmax = max(cmax, (uint64_t)(end - beg));
             }
         }
-        or_reduce_add(cn, cm, cor, cfull, cx, slot);
+        or_reduce_add(cn, cm, cor, cfull, cx, slot, cmax);
         if (!mp_sync(ctl, G, nbar, bar_ticks)) { fail = true; break; }
         // ---- B2: long rows take their parents from the frontier side
         if (ld_dev(&slot[M_HUBS])) {
@@ -716,7 +749,8 @@ __global__ __launch_bounds__(MP_BLOCK) void k_ms_persist(
             mfull += (int64_t)ld_dev(&slot[j * SLOT_LINE + M_MFULL]);
             exam += (int64_t)ld_dev(&slot[j * SLOT_LINE + M_EXAM]);
         }
-        last_or = ld_dev(&slot[M_OR]);
+        last_or = dslot_or(slot, M_OR);
+        maxdeg = (int64_t)dslot_max(slot, M_MAXDEG);
         // the slot of the level after next was last read at the previous level
         if (g == 0) {
             uint64_t* zs = ctr + (size_t)((done + 1) % SLOTS) * SLOT_WORDS;
@@ -757,6 +791,7 @@ __global__ __launch_bounds__(MP_BLOCK) void k_ms_persist(
             st->m_u = m_u;
             st->level = level;
             st->swapped = (F != Fa) ? 1 : 0;
+            st->maxdeg = maxdeg;
         }
     }
 }

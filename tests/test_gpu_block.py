@@ -164,8 +164,8 @@ def test_accumulator_is_reset_between_calls(orc):
 
 @pytest.mark.parametrize("mode", [-1, 0, 1])
 def test_union_modes_match_oracle(orc, mode):
-    """bfs_block_set_union: the accumulator (-1), the choice by density (0)
-    and the sorted union whenever it fits (1) give the oracle's pairs on
+    """bfs_block_set_union: the accumulator (-1 and the default 0) and the
+    sorted union whenever it fits (1) give the oracle's pairs on
     frontiers from one column to an eighth of the block; columns holding
     more than the sorted union's 8192 entries fall back to the accumulator,
     and the call after such a fallback is unaffected."""

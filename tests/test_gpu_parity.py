@@ -209,12 +209,45 @@ def test_column_blocked_bottom_up(orc, graphs, name, segments):
             check(orc, dg, s, p, d, True, ref)
 
 
+@pytest.mark.parametrize("name", ["kron12", "kron14", "er", "grid", "pieces", "complete"])
+@pytest.mark.parametrize("segments", [1, 2, 4, 8])
+def test_column_blocked_top_down(orc, graphs, name, segments):
+    """td_segments = S: a top-down level is expanded in S passes, one per
+    column segment in ascending order, each over the frontier's entries in
+    its id range (found by binary search in the sorted rows).  Every claim
+    mode gives the oracle's depths, minimum parents exactly, and the same
+    per-level schedule and counts."""
+    for off_dtype in (np.int32, np.int64):
+        dg = get(graphs, name, off_dtype)
+        for s in sources_for(dg.off, k=2, seed=51):
+            ref = orc.bfs_min(dg.off, dg.cols, int(s))
+            n_f, m_f, _ = orc.level_stats(dg.off, ref[1])
+            for dirv in (bfs.BFS_DIR_TD, bfs.BFS_DIR_DO):
+                for pm, claim in ((bfs.BFS_PARENT_MIN, 0), (bfs.BFS_PARENT_ANY, 0), (bfs.BFS_PARENT_ANY, 1),
+                                  (bfs.BFS_PARENT_ANY, 2)):
+                    p, d, st = dg.run(s, dir=dirv, parent_mode=pm, td_claim=claim, td_segments=segments,
+                                      td_seg_edges=1, small_edges=-1)
+                    check(orc, dg, s, p, d, pm == bfs.BFS_PARENT_MIN, ref)
+                    L = min(st.levels, bfs.STATS_MAX_LEVELS)
+                    assert list(st.level_nf[:L]) == n_f[:L].tolist()
+                    assert list(st.level_mf[:L]) == m_f[:L].tolist()
+
+
 def test_column_blocked_bad_segment_count():
     off, cols = path_graph(100)
     dg = DevGraph(off, cols)
     with pytest.raises(bfs.BfsError) as e:
         dg.run(0, bu_segments=9)
     assert e.value.status == 1
+    with pytest.raises(bfs.BfsError) as e:
+        dg.run(0, td_segments=9)
+    assert e.value.status == 1
+    # segments are sub-ranges of sorted rows
+    uns = DevGraph(off, cols, flags=bfs.BFS_GRAPH_SYMMETRIC)
+    for kw in (dict(bu_segments=2), dict(td_segments=2)):
+        with pytest.raises(bfs.BfsError) as e:
+            uns.run(0, **kw)
+        assert e.value.status == 8
 
 
 @pytest.mark.parametrize("name", ["kron12", "kron14", "er", "grid", "pieces", "star", "complete"])
@@ -253,6 +286,41 @@ def test_tuning_knobs_do_not_change_results(orc, graphs):
         for grid in (1, 7, 64, 4096):
             p, d, _ = dg.run(s, parent_mode=bfs.BFS_PARENT_MIN, bu_serial=serial, grid_blocks=grid)
             check(orc, dg, s, p, d, True, ref)
+
+
+@pytest.mark.parametrize("name", ["kron14", "er", "pieces", "grid"])
+def test_shape_knobs_do_not_change_results(orc, graphs, name):
+    """Workgroup and tile shapes (td_block, bu_block, bu_group) are tuning
+    only: minimum parents and depths stay the oracle's, any-parent trees stay
+    valid, and the per-level counts stay the oracle's."""
+    dg = get(graphs, name)
+    s = int(graphgen.random_sources(dg.off, 1, seed=13)[0])
+    ref = orc.bfs_min(dg.off, dg.cols, s)
+    n_f, m_f, _ = orc.level_stats(dg.off, ref[1])
+    runs = [dict(dir=bfs.BFS_DIR_TD, td_block=b, parent_mode=pm, td_claim=c)
+            for b in (128, 256, 512) for pm, c in ((bfs.BFS_PARENT_MIN, 0), (bfs.BFS_PARENT_ANY, 0),
+                                                   (bfs.BFS_PARENT_ANY, 2))]
+    runs += [dict(dir=dv, bu_block=b, bu_group=gw, parent_mode=pm)
+             for dv in (bfs.BFS_DIR_BU, bfs.BFS_DIR_DO) for b in (128, 256, 512) for gw in (0, 1, 8, 64)
+             for pm in (bfs.BFS_PARENT_MIN, bfs.BFS_PARENT_ANY)]
+    runs += [dict(td_block=b, bu_block=bb, grid_blocks=gb) for b in (128, 512) for bb in (128, 512)
+             for gb in (7, 1024)]
+    for kw in runs:
+        p, d, st = dg.run(s, **kw)
+        check(orc, dg, s, p, d, kw.get("parent_mode") == bfs.BFS_PARENT_MIN, ref)
+        L = min(st.levels, bfs.STATS_MAX_LEVELS)
+        assert list(st.level_nf[:L]) == n_f[:L].tolist(), kw
+        assert list(st.level_mf[:L]) == m_f[:L].tolist(), kw
+
+
+def test_shape_knob_errors():
+    off, cols = path_graph(100)
+    dg = DevGraph(off, cols)
+    for kw in (dict(td_block=64), dict(td_block=1024), dict(bu_block=192), dict(bu_group=3), dict(bu_group=128),
+               dict(bu_group=-1)):
+        with pytest.raises(bfs.BfsError) as e:
+            dg.run(0, **kw)
+        assert e.value.status == 1, kw
 
 
 @pytest.mark.parametrize("name", ["kron12", "pieces", "grid", "path"])
