@@ -471,8 +471,7 @@ def configs_bench(args):
                 from paper_1705_04590_amd import autotune
                 tuned = autotune.tune(g, graphgen.random_sources(off, 16, seed=99), k=1,
                                       cache_path=args.tune_cache, force=args.retune)
-                kw = {k: tuned[k] for k in ("alpha", "beta", "bu_serial", "grid_blocks", "td_claim", "small_edges",
-                                            "bu_head", "td_prepass") if k in tuned}
+                kw = {k: tuned[k] for k in autotune.KNOBS if k in tuned}
                 kw["dir"] = dv
                 tuning = "autotuned on 16 sources of seed 99" + (" (cached entry)" if tuned.get("cached") else "")
             t = singles(g, n, srcs, **kw)

@@ -86,7 +86,8 @@ enum {
     BFS_K_MS_LEVEL = 5,    /* multi-source level kernel                       */
     BFS_K_MS_OUTPUT = 6,   /* multi-source output kernels                     */
     BFS_K_BLOCK = 7,       /* DCSC block kernels                              */
-    BFS_KERNEL_KINDS = 8
+    BFS_K_FUSED = 8,       /* whole search in one persistent launch           */
+    BFS_KERNEL_KINDS = 9
 };
 
 #define BFS_STATS_MAX_LEVELS 64
@@ -118,12 +119,18 @@ typedef struct {
     int32_t small_edges;   /* top-down levels with at most this many frontier
                               edges run back to back inside one persistent
                               workgroup with no host round trip (0 = default
-                              1024, negative = no persistent engine at all)      */
+                              1024, negative = no persistent engine at all).
+                              bfs_run_multi: > 0 engine on, negative off, 0 on
+                              unless every row of the graph has at most 32
+                              entries (there the level kernels take one
+                              frontier vertex per thread and were measured
+                              faster)                                           */
     int32_t persist_edges; /* ... and up to this many inside persist_groups
                               workgroups separated by grid barriers (0 = default
-                              65536)                                             */
-    int32_t persist_groups;/* workgroups of that engine (0 = default 64; capped
-                              by what fits on the device at once)                */
+                              65536; bfs_run_multi: 2^18)                        */
+    int32_t persist_groups;/* workgroups of that engine and of the fused search
+                              (0 = default 64, fused search 128; capped by what
+                              fits on the device at once)                        */
     int32_t bu_head;       /* bottom-up, ANY parents, what each vertex probes
                               before scanning its row: 2 = its three
                               highest-degree neighbours; 3 = its two
@@ -178,6 +185,20 @@ typedef struct {
                               64, halved while the grid would get fewer than
                               two units per wave; the first sweep of a search
                               caps it at 8)                                    */
+    int32_t fused_max_n;   /* bfs_run on a graph with at most this many vertices
+                              runs the whole search, every level in both
+                              directions with the Section 4.4 rule on the
+                              device, in one persistent launch of
+                              persist_groups workgroups (0 = default: graphs
+                              up to 2^18 vertices, not with dir top-down only,
+                              whose heavy levels the level kernels balance
+                              better; positive = up to that many vertices in
+                              every direction; negative = never).  Used on BFS_GRAPH_SYMMETRIC
+                              graphs with fetch-or or minimum claims, bu_head
+                              0, td_prepass <= 0 and no column segments; the
+                              bottom-up scans follow row order.  When the
+                              device cannot hold the workgroups at once the
+                              search runs level by level instead              */
 } bfs_opts;
 
 typedef struct {

@@ -24,7 +24,7 @@ BFS_OK = 0
 BFS_DIR_DO, BFS_DIR_TD, BFS_DIR_BU = 0, 1, 2
 BFS_PARENT_ANY, BFS_PARENT_MIN = 0, 1
 BFS_GRAPH_SYMMETRIC, BFS_GRAPH_SORTED, BFS_GRAPH_VALIDATE = 0x1, 0x2, 0x4
-KERNEL_KINDS = ["init", "td_scan", "td_expand", "bu_sweep", "convert", "ms_level", "ms_output", "block"]
+KERNEL_KINDS = ["init", "td_scan", "td_expand", "bu_sweep", "convert", "ms_level", "ms_output", "block", "fused"]
 STATS_MAX_LEVELS = 64
 STATUS_NAMES = {0: "BFS_OK", 1: "BFS_E_INVALID_ARG", 2: "BFS_E_OUT_OF_RANGE", 3: "BFS_E_UNSORTED",
                 4: "BFS_E_NOT_SYMMETRIC", 5: "BFS_E_NO_MEMORY", 6: "BFS_E_HIP", 7: "BFS_E_BUDGET",
@@ -47,14 +47,14 @@ class bfs_opts(ctypes.Structure):
                 ("persist_edges", ctypes.c_int32), ("persist_groups", ctypes.c_int32),
                 ("bu_head", ctypes.c_int32), ("td_prepass", ctypes.c_int32), ("bu_segments", ctypes.c_int32),
                 ("td_segments", ctypes.c_int32), ("td_seg_edges", ctypes.c_int32), ("td_block", ctypes.c_int32),
-                ("bu_block", ctypes.c_int32), ("bu_group", ctypes.c_int32)]
+                ("bu_block", ctypes.c_int32), ("bu_group", ctypes.c_int32), ("fused_max_n", ctypes.c_int32)]
 
 
 class bfs_stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("td_levels", ctypes.c_int32), ("bu_levels", ctypes.c_int32),
                 ("fill_level", ctypes.c_int32), ("reached", ctypes.c_int64), ("isolated", ctypes.c_int64),
                 ("edges_examined", ctypes.c_int64),
-                ("total_ms", ctypes.c_double), ("launches", ctypes.c_int64 * 8), ("kernel_ms", ctypes.c_double * 8),
+                ("total_ms", ctypes.c_double), ("launches", ctypes.c_int64 * 9), ("kernel_ms", ctypes.c_double * 9),
                 ("level_dir", ctypes.c_int8 * STATS_MAX_LEVELS), ("level_nf", ctypes.c_int64 * STATS_MAX_LEVELS),
                 ("level_mf", ctypes.c_int64 * STATS_MAX_LEVELS), ("level_mu", ctypes.c_int64 * STATS_MAX_LEVELS),
                 ("level_unvisited", ctypes.c_int64 * STATS_MAX_LEVELS),

@@ -18,6 +18,8 @@ direction-invariant; the GPU tests check both):
   bu_block      threads per bottom-up sweep workgroup (256, 128, 512)
   bu_group      cap on the 64-vertex words of a bottom-up work unit (0 = automatic,
                 8, 16, 32)
+  fused_max_n   whole search in one persistent launch on small graphs: default size
+                limit (0) or never (-1)
 
 The search is a coordinate descent: (alpha, beta) on a grid first, then each
 remaining knob in turn, every candidate timed as the mean wall time of the
@@ -47,8 +49,9 @@ TD_SEGMENTS = (0, 2, 4)
 TD_BLOCKS = (0, 128, 512)
 BU_BLOCKS = (0, 128, 512)
 BU_GROUPS = (0, 8, 16, 32)
+FUSED = (0, -1)
 KNOBS = ("alpha", "beta", "bu_serial", "grid_blocks", "td_claim", "small_edges", "bu_head", "td_prepass",
-         "td_segments", "td_block", "bu_block", "bu_group")
+         "td_segments", "td_block", "bu_block", "bu_group", "fused_max_n")
 
 
 def _key(g, k: int) -> str:
@@ -108,7 +111,7 @@ def tune(g, sources, k: int = 1, cache_path: str | None = None, reps: int = 3, v
     best = {"alpha": 15.0, "beta": 18.0, "bu_serial": 16, "grid_blocks": 2048, "td_claim": 0, "small_edges": 0,
             "bu_head": 0, "td_prepass": 0}
     if k == 1:
-        best.update(td_segments=0, td_block=0, bu_block=0, bu_group=0)
+        best.update(td_segments=0, td_block=0, bu_block=0, bu_group=0, fused_max_n=0)
     trials = []
 
     def measure(cfg):
@@ -136,7 +139,7 @@ def tune(g, sources, k: int = 1, cache_path: str | None = None, reps: int = 3, v
                          ("td_prepass", PREPASS if k == 1 else ()),
                          ("td_segments", TD_SEGMENTS if k == 1 and g.flags & BFS_GRAPH_SORTED else ()),
                          ("td_block", TD_BLOCKS if k == 1 else ()), ("bu_block", BU_BLOCKS if k == 1 else ()),
-                         ("bu_group", BU_GROUPS if k == 1 else ())):
+                         ("bu_group", BU_GROUPS if k == 1 else ()), ("fused_max_n", FUSED if k == 1 else ())):
         for v in values:
             cfg = dict(best, **{name: v})
             if cfg == best:

@@ -76,11 +76,13 @@ struct bfs_graph {
     int32_t* d_hubid = nullptr;
     int4* d_hubr = nullptr;
     int nhub = 0;
+    int64_t max_degree = -1;   // longest row (symmetric graphs; -1 when not computed)
     bool hub_auto = false;   // frontier bitmap larger than the L2: ranked probes by default
     uint32_t* d_nbase = nullptr;   // per word: vertices with edges before it (head record index base)
     // workgroups of the persistent top-down engines that fit on the device
     int persist_groups_max = 1;
     int ms_groups_max = 1;
+    int fused_groups_max = 1;
     // host metadata
     uint64_t* h_buf = nullptr;              // pinned: create-time readback only
 };
@@ -177,7 +179,7 @@ SingleLayout single_layout(const bfs_graph* g) {
     L.pctr = o; o = align_up(o + sizeof(uint64_t) * SLOTS * SLOT_WORDS);
     L.small = o; o = align_up(o + sizeof(SmallState));
     L.ctl_end = o;
-    L.rec = o; o = align_up(o + sizeof(int64_t) * 4 * BFS_STATS_MAX_LEVELS);
+    L.rec = o; o = align_up(o + sizeof(int64_t) * 6 * BFS_STATS_MAX_LEVELS);   // 4 per level (top-down engine), 6 (fused)
     L.visited = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
     L.vprev = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
     L.fbits = o; o = align_up(o + sizeof(uint64_t) * (size_t)W);
@@ -374,6 +376,66 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     HostCtx* ctx = nullptr;
     HIP_TRY(host_ctx(&ctx));
     Timer T{ctx, stream, o.timing, {}, 0};
+
+    // a small graph: the whole search in one persistent launch
+    const int64_t fused_max = o.fused_max_n > 0                            ? o.fused_max_n
+                              : o.fused_max_n == 0 && o.dir != BFS_DIR_TD ? FUSED_MAX_N
+                                                                          : -1;
+    if (n <= fused_max && (g->flags & BFS_GRAPH_SYMMETRIC) && g->d_iso &&
+        (claim_mode == CLAIM_BITMAP || claim_mode == CLAIM_MIN) && o.bu_head == 0 && o.td_prepass <= 0 &&
+        o.bu_segments == 0 && o.td_segments == 0) {
+        int64_t groups = o.persist_groups > 0 ? o.persist_groups : FUSED_GROUPS;
+        groups = std::min<int64_t>(groups, g->fused_groups_max);
+        groups = std::min<int64_t>(groups, (W + 3) / 4);   // at least one word per wave
+        if (groups < 1) groups = 1;
+        const int rec_cap = st ? BFS_STATS_MAX_LEVELS : 0;
+        FusedState* d_fs = (FusedState*)(ws + Lo.small);
+        int64_t* d_rec = (int64_t*)(ws + Lo.rec);
+        HIP_TRY(T.begin(BFS_K_FUSED));
+        launch_clear_words(L, counters, (int64_t)((Lo.ctl_end - Lo.counters) / sizeof(uint64_t)));
+        launch_search_fused<OffT>(L, claim_mode == CLAIM_MIN, (int)groups, off, g->cols, g->d_iso, n, g->nnz, src, parent,
+                                  depth, visited, fbits, nbits, vprev, o.dir, o.alpha, o.beta, serial, d_fs, counters,
+                                  (PersistCtl*)(ws + Lo.pctl), d_rec, rec_cap);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(T.end(BFS_K_FUSED, -1));
+        const uint64_t* hb = nullptr;
+        {
+            const int nw = (int)(((Lo.rec - Lo.small) + sizeof(int64_t) * 6 * (size_t)rec_cap) / sizeof(uint64_t));
+            bfs_status rs = readback(ctx, stream, d_fs, nw, &hb);
+            if (rs != BFS_OK) return rs;
+        }
+        FusedState fs;
+        std::memcpy(&fs, hb, sizeof(fs));
+        if (fs.reason == ENG_TIMEOUT) return fail(BFS_E_HIP, "fused search: grid barrier timed out");
+        if (fs.reason != ENG_NOT_RUN) {
+            if (st) {
+                const int64_t* r = (const int64_t*)((const char*)hb + (Lo.rec - Lo.small));
+                for (int64_t d = 0; d < fs.levels_done && d < rec_cap; ++d, r += 6) {
+                    st->level_dir[d] = (int8_t)r[0];
+                    st->level_nf[d] = r[1];
+                    st->level_mf[d] = r[2];
+                    st->level_mu[d] = r[3];
+                    st->level_unvisited[d] = r[4];
+                    st->level_examined[d] = r[5];
+                    if (r[0]) st->bu_levels++; else st->td_levels++;
+                }
+                st->launches[BFS_K_FUSED] += 1;
+                st->levels = (int32_t)fs.levels_done;
+                st->fill_level = -1;
+                st->reached = fs.reached;
+                st->isolated = g->isolated;
+                st->edges_examined = fs.examined;
+                if (T.mode) {
+                    if (!T.recs.empty()) HIP_TRY(hipEventSynchronize(ctx->events[T.recs.back().ev + 1]));
+                    T.collect(st);
+                }
+                st->total_ms =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+            }
+            return BFS_OK;
+        }
+        // the workgroups could not all be resident: level by level instead
+    }
 
     // degree of the source: the first frontier's edge count
     const uint64_t* h = nullptr;   // the last level's counters, in the mailbox
@@ -803,7 +865,10 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
     int64_t examined = 0, reached_pairs = 0;
     // persistent engine for runs of small top-down levels (the same knobs as
     // the single-source engine: small_edges < 0 switches it off)
-    bool engine_on = o.small_edges >= 0;
+    // on graphs whose rows are all short the level kernels take one frontier
+    // vertex per thread, and the engine is off unless asked for
+    const bool short_rows = g->max_degree >= 0 && g->max_degree <= MS_ROWS_MAX_DEG;
+    bool engine_on = o.small_edges > 0 || (o.small_edges == 0 && !short_rows);
     // edge cap of an engine level: the first level of a run is also held to
     // 2^16 edges and the later ones to rows of at most 4096 entries
     const int64_t eng_cap = o.persist_edges > 0 ? o.persist_edges : ((int64_t)1 << 18);
@@ -914,7 +979,7 @@ bfs_status run_multi(bfs_graph* g, const int64_t* h_src, int k, const bfs_opts& 
             HIP_TRY(T.begin(BFS_K_MS_LEVEL));
             if (m_f > 0)
                 launch_ms_td<OffT>(L, off, g->cols, g->nnz, qa, qlen, m_f, scan, tiles, partial, F, N, visited, full,
-                                   qb, par_vm, lvl_vm, next_level, serial, hubmark, slot, zslot);
+                                   qb, par_vm, lvl_vm, next_level, serial, hubmark, slot, zslot, g->max_degree);
             HIP_TRY(hipGetLastError());
             HIP_TRY(T.end(BFS_K_MS_LEVEL, level));
             if (st) { st->launches[BFS_K_CONVERT] += conv; st->launches[BFS_K_MS_LEVEL] += m_f > 0 ? 3 : 0; }
@@ -1029,6 +1094,9 @@ bfs_status build_derived(bfs_graph* g, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(hh.data(), hist.p, sizeof(uint32_t) * HUB_HIST_BINS, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     int64_t nhub = 0, thr = 0;
+    g->max_degree = 0;
+    for (int64_t d = HUB_HIST_BINS - 1; d >= 1; --d)
+        if (hh[d]) { g->max_degree = d; break; }   // the last bin holds every longer row too
     for (int64_t d = HUB_HIST_BINS - 1; d >= 1; --d) {
         if (nhub + hh[d] > HUB_BITS - 1) break;
         nhub += hh[d];
@@ -1167,6 +1235,7 @@ bfs_status bfs_create_graph_csr(int64_t n, const void* d_offsets, int offset_byt
     }
     g->persist_groups_max = g->off_bytes == 4 ? persist_max_groups<int32_t>() : persist_max_groups<int64_t>();
     g->ms_groups_max = g->off_bytes == 4 ? ms_persist_max_groups<int32_t>() : ms_persist_max_groups<int64_t>();
+    g->fused_groups_max = g->off_bytes == 4 ? fused_max_groups<int32_t>() : fused_max_groups<int64_t>();
     {
         // hub-ranked probes pay off only when the frontier bitmap does not fit in L2
         int l2 = 0;

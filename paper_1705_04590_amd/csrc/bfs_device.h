@@ -249,8 +249,12 @@ __device__ __forceinline__ bool roll_call(PersistCtl* ctl, uint32_t G, long long
 }
 
 // Grid barrier number `k` (0, 1, 2, ...): false on timeout (error flag set).
+// Every wave first waits for its own memory operations to complete (the
+// workgroup barrier alone does not wait for global stores and atomics whose
+// results are unused), so thread 0's release covers the whole workgroup.
 __device__ __forceinline__ bool grid_sync(PersistCtl* ctl, uint32_t G, uint32_t k, long long ticks) {
     __shared__ int s_ok;
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (G == 1) return true;
     if (threadIdx.x == 0) {

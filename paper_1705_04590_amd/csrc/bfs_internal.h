@@ -182,6 +182,28 @@ struct SmallState {                                 // written by the engine
 struct PersistCtl {
     uint32_t roll, bar, err, pad;
 };
+// the fused whole-search engine's result (in the engine state area)
+struct FusedState {
+    int64_t levels_done, reason, reached, examined, level;
+};
+// graphs of at most this many vertices run the fused search by default
+constexpr int64_t FUSED_MAX_N = (int64_t)1 << 18;
+constexpr int FUSED_GROUPS = 128;   // default workgroups of the fused search
+// most workgroups of the fused search that fit on the device at once
+template <typename OffT>
+int fused_max_groups();
+// One whole search (every level, both directions) in one launch.  ctr and
+// ctl zero at launch; st reads ENG_NOT_RUN until the engine writes it (then
+// levels_done, reason, reached, examined as a FusedState); rec: 6 int64 per
+// level (direction, n_f, m_f, m_u, unvisited, entries examined); b0..b2:
+// three n/64-word frontier bitmaps.  dir: 0 the Section 4.4 rule, 1
+// top-down only, 2 bottom-up only.
+template <typename OffT>
+void launch_search_fused(const Launch& L, bool min_parent, int groups, const OffT* off, const int32_t* cols,
+                         const uint64_t* iso, int64_t n, int64_t nnz, int64_t src, int32_t* parent, int32_t* depth,
+                         uint64_t* visited, uint64_t* b0, uint64_t* b1, uint64_t* b2, int dir, double alpha,
+                         double beta, int serial, FusedState* st, uint64_t* ctr, PersistCtl* ctl, int64_t* rec,
+                         int rec_cap);
 // most workgroups of the engine that fit on the device at once
 template <typename OffT>
 int persist_max_groups();
@@ -216,11 +238,16 @@ template <typename OffT>
 void launch_ms_init(const Launch& L, const OffT* off, int64_t n, int k, const int64_t* src, const uint64_t* iso,
                     uint64_t* visited, uint64_t* F, uint64_t* N, int32_t* par_vm, uint16_t* lvl_vm, int32_t* q,
                     uint64_t* counters, uint64_t* slot0);
+// max_degree: the graph's longest row (-1 unknown).  Rows of at most
+// MS_ROWS_MAX_DEG entries everywhere: the expand takes one frontier vertex
+// per thread (no degree scan); no row longer than the hub limit: the hub
+// passes are not launched.
 template <typename OffT>
 void launch_ms_td(const Launch& L, const OffT* off, const int32_t* cols, int64_t nnz, const int32_t* q, int64_t qlen,
                   int64_t total, int64_t* scan, int32_t* tiles, int64_t* partial, const uint64_t* F, uint64_t* N,
                   uint64_t* visited, uint64_t full, int32_t* qnext, int32_t* par_vm, uint16_t* lvl_vm,
-                  uint16_t level, int serial, uint64_t* hubmark, uint64_t* slot, uint64_t* zslot);
+                  uint16_t level, int serial, uint64_t* hubmark, uint64_t* slot, uint64_t* zslot,
+                  int64_t max_degree);
 template <typename OffT>
 void launch_ms_bu(const Launch& L, const OffT* off, const int32_t* cols, int64_t n, const uint64_t* F, uint64_t* N,
                   uint64_t* visited, uint64_t full, const uint64_t* active_dev, int32_t* par_vm, uint16_t* lvl_vm,
@@ -231,6 +258,7 @@ void launch_ms_mask_to_queue(const Launch& L, const uint64_t* N, int64_t n, int3
 // queue chunk), and while the rows' lengths are not known only up to
 // MS_ENGINE_FIRST_CAP frontier edges.
 constexpr int64_t MS_ENGINE_MAX_DEG = 4096;
+constexpr int MS_ROWS_MAX_DEG = 32;
 constexpr int64_t MS_ENGINE_FIRST_CAP = 65536;
 // persistent multi-source top-down engine: inputs, and the state it leaves
 struct MsIn {

@@ -29,6 +29,7 @@ enum { M_QLEN = 0, M_NNEXT = 1, M_MNEXT = 2, M_OR = 3, M_MFULL = 4, M_EXAM = 5, 
 // rows longer than this are not scanned by the resolve pass: their parents
 // come from the frontier side instead (k_ms_hub_resolve)
 constexpr int64_t MS_HUB_ROW = 512;
+constexpr int MS_ROWS_BLOCK = 256;
 
 // Workgroup totals added once per workgroup to its line of the slot (sums;
 // the OR of the new-source bits; the maximum row length `mx`).  Every word is
@@ -232,6 +233,50 @@ __global__ __launch_bounds__(TD_BLOCK) void k_ms_td_expand(
 // whole wave on the rows still open.  Returns the bits found; *examined gets
 // the entries looked at up to the last needed supplier (or the row length).
 // Must be called by all lanes of the wave.
+// Top-down on a graph whose rows are all short (at most MS_ROWS_MAX_DEG
+// entries): one frontier vertex per thread, no degree scan.  The same claims
+// as k_ms_td_expand: the sources of u not yet at v are OR-ed into N[v], and v
+// joins the next queue when N[v] was zero.  A block's new vertices collect in
+// LDS (at most MS_ROWS_BLOCK * MS_ROWS_MAX_DEG of them) and go to the queue
+// with one global atomic per block and step.
+template <typename OffT>
+__global__ __launch_bounds__(MS_ROWS_BLOCK) void k_ms_td_rows(
+    const OffT* __restrict__ off, const int32_t* __restrict__ cols, const int32_t* __restrict__ q, int64_t qlen,
+    const uint64_t* __restrict__ F, const uint64_t* __restrict__ visited, uint64_t* __restrict__ N,
+    int32_t* __restrict__ qnext, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot) {
+    __shared__ int32_t s_out[MS_ROWS_BLOCK * MS_ROWS_MAX_DEG];
+    __shared__ int s_cnt;
+    __shared__ uint64_t s_base;
+    zero_slot(zslot);
+    const int64_t stride = (int64_t)gridDim.x * MS_ROWS_BLOCK;
+    for (int64_t i0 = (int64_t)blockIdx.x * MS_ROWS_BLOCK; i0 < qlen; i0 += stride) {
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        const int64_t i = i0 + threadIdx.x;
+        int64_t b = 0, e = 0;
+        uint64_t f = 0;
+        if (i < qlen) {
+            const int32_t u = q[i];
+            b = (int64_t)off[u];
+            e = (int64_t)off[u + 1];
+            f = F[u];
+        }
+        for (int64_t p = b; p < e; ++p) {
+            const int32_t v = cols[p];
+            const uint64_t x = f & ~visited[v];
+            if (x && atomicOr((unsigned long long*)&N[v], (unsigned long long)x) == 0ull)
+                s_out[atomicAdd(&s_cnt, 1)] = v;
+        }
+        __syncthreads();
+        const int cnt = s_cnt;
+        if (threadIdx.x == 0 && cnt > 0)
+            s_base = atomicAdd((unsigned long long*)&slot[M_QLEN], (unsigned long long)cnt);
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt; j += MS_ROWS_BLOCK) qnext[s_base + j] = s_out[j];
+        __syncthreads();
+    }
+}
+
 __device__ __forceinline__ uint64_t first_suppliers(const int32_t* __restrict__ cols, const uint64_t* __restrict__ F,
                                                     int64_t v, int64_t beg, int64_t end, uint64_t need, int serial,
                                                     int32_t* __restrict__ par_vm, uint16_t* __restrict__ lvl_vm,
@@ -901,21 +946,32 @@ template <typename OffT>
 void launch_ms_td(const Launch& L, const OffT* off, const int32_t* cols, int64_t nnz, const int32_t* q, int64_t qlen,
                   int64_t total, int64_t* scan, int32_t* tiles, int64_t* partial, const uint64_t* F, uint64_t* N,
                   uint64_t* visited, uint64_t full, int32_t* qnext, int32_t* par_vm, uint16_t* lvl_vm,
-                  uint16_t level, int serial, uint64_t* hubmark, uint64_t* slot, uint64_t* zslot) {
-    launch_scan(L.stream, QueueDegree<OffT>{off, q}, (const uint64_t*)nullptr, qlen, partial,
-                TileSink{scan, tiles, nullptr});
+                  uint16_t level, int serial, uint64_t* hubmark, uint64_t* slot, uint64_t* zslot,
+                  int64_t max_degree) {
     const int64_t ntiles = (total + TD_TILE - 1) / TD_TILE;
     const int g = grid_for(ntiles, 1, L.grid_cap);
-    hipLaunchKernelGGL(k_ms_td_expand<OffT>, dim3(g), dim3(TD_BLOCK), 0, L.stream,
-                       off, cols, q, qlen, scan, tiles, total, nnz, F, visited, N, qnext, slot, zslot);
-    // the next queue's length is in slot[M_QLEN], written by the expand
-    hipLaunchKernelGGL(k_ms_resolve<OffT>, dim3(L.grid_cap), dim3(256), 0, L.stream, off, cols, qnext,
-                       (const uint64_t*)&slot[M_QLEN], F, N, visited, full, par_vm, lvl_vm, level, serial, hubmark,
-                       slot);
-    hipLaunchKernelGGL(k_ms_hub_resolve<OffT>, dim3(g), dim3(TD_BLOCK), 0, L.stream, off, cols, q, qlen, scan, tiles,
-                       total, nnz, F, N, hubmark, par_vm, (const uint64_t*)&slot[M_HUBS]);
-    hipLaunchKernelGGL(k_ms_hub_clear, dim3(L.grid_cap), dim3(256), 0, L.stream, qnext, (const uint64_t*)&slot[M_QLEN],
-                       hubmark, (const uint64_t*)&slot[M_HUBS]);
+    if (max_degree >= 0 && max_degree <= MS_ROWS_MAX_DEG) {
+        hipLaunchKernelGGL(k_ms_td_rows<OffT>, dim3(grid_for(qlen, MS_ROWS_BLOCK, L.grid_cap)), dim3(MS_ROWS_BLOCK),
+                           0, L.stream, off, cols, q, qlen, F, visited, N, qnext, slot, zslot);
+    } else {
+        launch_scan(L.stream, QueueDegree<OffT>{off, q}, (const uint64_t*)nullptr, qlen, partial,
+                    TileSink{scan, tiles, nullptr});
+        hipLaunchKernelGGL(k_ms_td_expand<OffT>, dim3(g), dim3(TD_BLOCK), 0, L.stream,
+                           off, cols, q, qlen, scan, tiles, total, nnz, F, visited, N, qnext, slot, zslot);
+    }
+    // the next queue's length is in slot[M_QLEN], written by the expand; at
+    // most `total` vertices are new
+    hipLaunchKernelGGL(k_ms_resolve<OffT>, dim3(grid_for(total, 256, L.grid_cap)), dim3(256), 0, L.stream, off, cols,
+                       qnext, (const uint64_t*)&slot[M_QLEN], F, N, visited, full, par_vm, lvl_vm, level, serial,
+                       hubmark, slot);
+    // rows longer than the hub limit exist: the hub passes (over the degree
+    // scan's tiles, which the row-per-thread expand never needs here)
+    if (max_degree < 0 || max_degree > MS_HUB_ROW) {
+        hipLaunchKernelGGL(k_ms_hub_resolve<OffT>, dim3(g), dim3(TD_BLOCK), 0, L.stream, off, cols, q, qlen, scan,
+                           tiles, total, nnz, F, N, hubmark, par_vm, (const uint64_t*)&slot[M_HUBS]);
+        hipLaunchKernelGGL(k_ms_hub_clear, dim3(L.grid_cap), dim3(256), 0, L.stream, qnext,
+                           (const uint64_t*)&slot[M_QLEN], hubmark, (const uint64_t*)&slot[M_HUBS]);
+    }
 }
 
 template <typename OffT>
@@ -951,7 +1007,7 @@ void launch_ms_output(const Launch& L, int64_t n, int k, const int64_t* src, con
     template void launch_ms_td<T>(const Launch&, const T*, const int32_t*, int64_t, const int32_t*, int64_t,       \
                                   int64_t, int64_t*, int32_t*, int64_t*, const uint64_t*, uint64_t*, uint64_t*,    \
                                   uint64_t, int32_t*, int32_t*, uint16_t*, uint16_t, int, uint64_t*, uint64_t*,    \
-                                  uint64_t*);                                                                      \
+                                  uint64_t*, int64_t);                                                             \
     template void launch_ms_bu<T>(const Launch&, const T*, const int32_t*, int64_t, const uint64_t*, uint64_t*,    \
                                   uint64_t*, uint64_t, const uint64_t*, int32_t*, uint16_t*, uint16_t, int,        \
                                   uint64_t*, uint64_t*);

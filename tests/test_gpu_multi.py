@@ -164,9 +164,12 @@ def test_multi_long_rows_get_minimum_parents(orc):
             check_all(orc, mg, srcs, p, d)
 
 
-# (small_edges, persist_edges, persist_groups): engine off, default, tiny and
-# huge edge caps, one workgroup, counts that do not divide the queue evenly
-MS_ENGINE = ((-1, 0, 0), (0, 0, 0), (0, 1, 0), (0, 100, 3), (0, 1 << 30, 1), (0, 1 << 30, 64), (0, 5000, 7))
+# (small_edges, persist_edges, persist_groups): engine off, default, on (a
+# positive small_edges; graphs whose rows all have at most 32 entries leave it
+# off by default) with tiny and huge edge caps, one workgroup, counts that do
+# not divide the queue evenly
+MS_ENGINE = ((-1, 0, 0), (0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 100, 3), (1, 1 << 30, 1), (1, 1 << 30, 64),
+             (1, 5000, 7))
 
 
 @pytest.mark.parametrize("name", ["kron12", "grid", "er"])
@@ -202,7 +205,7 @@ def test_multi_engine_on_a_long_grid():
     mg = MG(off, cols)
     srcs = [0, W - 1, (H - 1) * W, H * W - 1, W // 2, W + 700]
     r, c = np.divmod(np.arange(H * W), W)
-    for eng in (0, -1):
+    for eng in (1, 0, -1):
         p, d, st = mg.multi(srcs, small_edges=eng)
         for j, s in enumerate(srcs):
             r0, c0 = divmod(s, W)

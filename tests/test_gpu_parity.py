@@ -34,6 +34,9 @@ class DevGraph:
         self.depth = torch.empty(max(self.n, 1), dtype=torch.int32, device=DEV)
 
     def run(self, s, **kw):
+        # the level-by-level kernels unless a test asks for the fused search
+        # (which small graphs take by default; its own tests below)
+        kw.setdefault("fused_max_n", -1)
         # poison the outputs: every entry must be written by the call itself
         self.parent.fill_(-7)
         self.depth.fill_(-7)
@@ -321,6 +324,72 @@ def test_shape_knob_errors():
         with pytest.raises(bfs.BfsError) as e:
             dg.run(0, **kw)
         assert e.value.status == 1, kw
+
+
+FUSED = bfs.KERNEL_KINDS.index("fused")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fused_search_parity(orc, graphs, name):
+    """The whole search in one persistent launch (fused_max_n): oracle depths,
+    minimum parents exactly, valid any-parent trees, and the oracle's level
+    schedule and counts (frontier size and edges, unvisited vertices and
+    edges, bottom-up entries examined in row order), in every direction
+    policy, from isolated sources too, with 1 to 64 workgroups."""
+    for off_dtype in (np.int32, np.int64):
+        dg = get(graphs, name, off_dtype)
+        for s in sources_for(dg.off, k=2, seed=71):
+            ref = orc.bfs_min(dg.off, dg.cols, int(s))
+            n_f, m_f, m_u = orc.level_stats(dg.off, ref[1])
+            for dirv, alpha, beta in ((bfs.BFS_DIR_DO, 15.0, 18.0), (bfs.BFS_DIR_TD, 15.0, 18.0),
+                                      (bfs.BFS_DIR_BU, 15.0, 18.0), (bfs.BFS_DIR_DO, 2.0, 50.0),
+                                      (bfs.BFS_DIR_DO, 1e9, 1e9)):
+                for pm in (bfs.BFS_PARENT_MIN, bfs.BFS_PARENT_ANY):
+                    for groups in (0, 1, 3):
+                        p, d, st = dg.run(s, dir=dirv, alpha=alpha, beta=beta, parent_mode=pm,
+                                          fused_max_n=1 << 30, persist_groups=groups)
+                        assert st.launches[FUSED] == 1 and st.launches[bfs.KERNEL_KINDS.index("bu_sweep")] == 0
+                        check(orc, dg, s, p, d, pm == bfs.BFS_PARENT_MIN, ref)
+                        assert st.levels == len(n_f) and st.fill_level == -1
+                        assert st.reached == int((d >= 0).sum())
+                        L = min(st.levels, bfs.STATS_MAX_LEVELS)
+                        if dirv == bfs.BFS_DIR_DO:
+                            sched = orc.direction_schedule(dg.n, n_f, m_f, m_u, alpha, beta)
+                        else:
+                            sched = np.full(len(n_f), 1 if dirv == bfs.BFS_DIR_BU else 0)
+                        assert list(st.level_dir[:L]) == sched[:L].tolist()
+                        assert list(st.level_nf[:L]) == n_f[:L].tolist()
+                        assert list(st.level_mf[:L]) == m_f[:L].tolist()
+                        assert list(st.level_mu[:L]) == m_u[:L].tolist()
+                        assert st.td_levels + st.bu_levels == L
+                        for lv in range(L):
+                            if st.level_dir[lv] == 1:
+                                scanned, unvisited = orc.bu_scan_lengths(dg.off, dg.cols, d, lv)
+                                assert st.level_examined[lv] == scanned
+                                assert st.level_unvisited[lv] == unvisited
+                            else:
+                                assert st.level_examined[lv] == m_f[lv]
+
+
+def test_fused_search_selection(orc, graphs):
+    """The fused search is the default up to 2^18 vertices (not for top-down
+    only, unless a size limit is given) and is not used when switched off,
+    above the size limit, or with knobs it does not take (CAS or benign
+    claims, explicit heads, pre-pass, column segments)."""
+    dg = get(graphs, "kron12")
+    s = int(graphgen.random_sources(dg.off, 1, seed=5)[0])
+    ref = orc.bfs_min(dg.off, dg.cols, s)
+    for kw in (dict(fused_max_n=0), dict(fused_max_n=0, dir=bfs.BFS_DIR_BU), dict(fused_max_n=dg.n, dir=bfs.BFS_DIR_TD)):
+        _, _, st = dg.run(s, **kw)
+        assert st.launches[FUSED] == 1, kw
+    for kw in (dict(fused_max_n=-1), dict(fused_max_n=dg.n - 1), dict(td_claim=1), dict(td_claim=2),
+               dict(bu_head=2), dict(td_prepass=1), dict(bu_segments=2), dict(td_segments=2),
+               dict(dir=bfs.BFS_DIR_TD)):
+        p, d, st = dg.run(s, **dict(dict(fused_max_n=0), **kw))
+        assert st.launches[FUSED] == 0, kw
+        check(orc, dg, s, p, d, False, ref)
+    _, _, st = dg.run(s, fused_max_n=dg.n)
+    assert st.launches[FUSED] == 1
 
 
 @pytest.mark.parametrize("name", ["kron12", "pieces", "grid", "path"])
