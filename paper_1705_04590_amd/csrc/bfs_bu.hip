@@ -42,6 +42,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 __device__ __forceinline__ bool bit_of(uint64_t word, int32_t c) { return (word >> (c & 63)) & 1ull; }
 
 __device__ __forceinline__ uint64_t stream_load(const uint64_t* p) { return __builtin_nontemporal_load(p); }
+// a head record read once per level: marked non-temporal, so the streamed
+// records do not push the frontier bitmap's lines out of the L2
+__device__ __forceinline__ int4 stream_load4(const int4* p) {
+    typedef int v4 __attribute__((ext_vector_type(4)));
+    const v4 x = __builtin_nontemporal_load((const v4*)p);
+    return make_int4(x.x, x.y, x.z, x.w);
+}
 
 // HUB = 0: `head` holds each row's first three entries (row order, as the
 // minimum-id parent needs).  HUB = 1 (any-parent searches): it holds the three
@@ -107,8 +114,10 @@ __device__ __forceinline__ void bu_sweep_body(
     // v found its parent at row position pos
     auto found = [&](int32_t v, int32_t par, int32_t pos, int32_t deg) {
         if (!FILL) {
-            parent[v] = par;
-            depth[v] = next_depth;
+            // scattered single entries: non-temporal stores, which cost less
+            // than partial lines left dirty in the L2 for a later write-back
+            __builtin_nontemporal_store(par, &parent[v]);
+            __builtin_nontemporal_store(next_depth, &depth[v]);
         }
         atomicOr(&nbw[(v >> 6) - w0], 1ull << (v & 63));
         my_n += 1;
@@ -147,14 +156,14 @@ __device__ __forceinline__ void bu_sweep_body(
             // heads of the first round; later rounds are prefetched one ahead
             int32_t v_next = lane < nw ? list[lane] : 0;
             int4 h_next = make_int4(0, -1, -1, -1);
-            if (lane < nw) h_next = head[hlist[lane]];
+            if (lane < nw) h_next = stream_load4(&head[hlist[lane]]);
             for (int r = 0; r < nw; r += WAVE) {
                 const bool act = r + lane < nw;
                 const int32_t v = v_next;
                 const int4 h = h_next;
                 if (r + WAVE + lane < nw) {
                     v_next = list[r + WAVE + lane];
-                    h_next = head[hlist[r + WAVE + lane]];
+                    h_next = stream_load4(&head[hlist[r + WAVE + lane]]);
                 }
                 const int deg = act ? h.x : 0;
                 int32_t par = -1;
@@ -463,8 +472,8 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_segment(
         }
         if (act) {
             if (par >= 0) {
-                parent[v] = par;
-                depth[v] = next_depth;
+                __builtin_nontemporal_store(par, &parent[v]);
+                __builtin_nontemporal_store(next_depth, &depth[v]);
                 const unsigned long long bit = 1ull << (v & 63);
                 __hip_atomic_fetch_or((unsigned long long*)&nbits[v >> 6], bit, __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);

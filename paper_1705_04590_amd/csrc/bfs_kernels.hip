@@ -322,7 +322,9 @@ __global__ __launch_bounds__(BLK) void k_td_expand(
                     pos = (int64_t)off[u] + (segpos ? (int64_t)segpos[lo] : 0) + (e - scan[lo]);
                 }
                 if (pos < 0 || pos >= nnz) pos = 0;   // unreachable for a consistent scan
-                vv[k] = cols[pos];
+                // streamed once: non-temporal, so the columns do not push the
+                // visited bitmap's lines out of the L2
+                vv[k] = __builtin_nontemporal_load(&cols[pos]);
             }
         }
         // one probe of the visited bitmap per edge; ANY modes claim on that
@@ -351,13 +353,14 @@ __global__ __launch_bounds__(BLK) void k_td_expand(
                     // written stays; the bit is set by an atomic whose old
                     // value is not waited for, so later probes skip v
                     won[k] = true;
-                    parent[v] = uu[k];
+                    __builtin_nontemporal_store(uu[k], &parent[v]);
                     __hip_atomic_fetch_or((unsigned long long*)&visited[v >> 6], (unsigned long long)bit,
                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 } else {
                     const uint64_t old = atomicOr((unsigned long long*)&visited[v >> 6], (unsigned long long)bit);
                     won[k] = !(old & bit);
-                    if (won[k]) parent[v] = uu[k];
+                    // scattered single entries: non-temporal stores (see below)
+                    if (won[k]) __builtin_nontemporal_store(uu[k], &parent[v]);
                 }
             }
         }
@@ -366,7 +369,10 @@ __global__ __launch_bounds__(BLK) void k_td_expand(
             const int32_t v = vv[k];
             int64_t dv = 0;
             if (won[k]) {
-                depth[v] = next_depth;
+                // a winner's entries are scattered single words: stored
+                // non-temporally, they cost less than partial lines left dirty
+                // in the L2 for a later write-back
+                __builtin_nontemporal_store(next_depth, &depth[v]);
                 dv = (int64_t)off[v + 1] - (int64_t)off[v];
                 my_n += 1;
                 my_m += (uint64_t)dv;
