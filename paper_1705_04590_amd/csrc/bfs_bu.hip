@@ -32,6 +32,7 @@ namespace bfsk {
 
 constexpr int BU_WIN = 512;   // compacted-list window per wave (entries)
 constexpr int FILL_GW = BU_WIN / WAVE;   // words per group of a sweep that writes the fill
+constexpr int BU_PB = 2;   // rounds of 64 heads whose loads and probes are in flight together
 
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -153,32 +154,55 @@ __device__ __forceinline__ void bu_sweep_body(
             }
             wave_lds_sync();
             int nmiss = 0;   // rows compacted for the second pass (wave-uniform)
-            // heads of the first round; later rounds are prefetched one ahead
-            int32_t v_next = lane < nw ? list[lane] : 0;
-            int4 h_next = make_int4(0, -1, -1, -1);
-            if (lane < nw) h_next = stream_load4(&head[hlist[lane]]);
-            for (int r = 0; r < nw; r += WAVE) {
-                const bool act = r + lane < nw;
-                const int32_t v = v_next;
-                const int4 h = h_next;
-                if (r + WAVE + lane < nw) {
-                    v_next = list[r + WAVE + lane];
-                    h_next = stream_load4(&head[hlist[r + WAVE + lane]]);
+            // heads are taken BU_PB rounds of 64 at a time: their loads, then
+            // their probes, are all in flight together, and the rounds are
+            // then settled in order
+            for (int r0 = 0; r0 < nw; r0 += BU_PB * WAVE) {
+                int32_t vb[BU_PB];
+                int4 hb[BU_PB];
+#pragma unroll
+                for (int j = 0; j < BU_PB; ++j) {
+                    const int idx = r0 + j * WAVE + lane;
+                    vb[j] = 0;
+                    hb[j] = make_int4(0, -1, -1, -1);
+                    if (idx < nw) {
+                        vb[j] = list[idx];
+                        hb[j] = stream_load4(&head[hlist[idx]]);
+                    }
                 }
+                // entries the head probes; with HUB = 2 its last word holds ranks
+                constexpr int32_t nprobe = HUB >= 2 ? 2 : 3;
+                // the first probe of every round (and with HUB = 2 the second
+                // too) before any is tested
+                uint64_t fa[BU_PB], fb[BU_PB];
+#pragma unroll
+                for (int j = 0; j < BU_PB; ++j) {
+                    const int4 h = hb[j];
+                    const int deg = h.x;
+                    if (HUB >= 2) {
+                        const uint32_t q0 = (uint32_t)h.w & 0xFFFFu, q1 = (uint32_t)h.w >> 16;
+                        fa[j] = deg > 0 ? (q0 != 0xFFFFu ? s_hb[q0 >> 6] : fbits[h.y >> 6]) : 0ull;
+                        fb[j] = deg > 1 ? (q1 != 0xFFFFu ? s_hb[q1 >> 6] : fbits[h.z >> 6]) : 0ull;
+                    } else {
+                        fa[j] = deg > 0 ? fbits[h.y >> 6] : 0ull;
+                        fb[j] = 0ull;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < BU_PB; ++j) {
+                const int r = r0 + j * WAVE;
+                const bool act = r + lane < nw;
+                const int32_t v = vb[j];
+                const int4 h = hb[j];
                 const int deg = act ? h.x : 0;
                 int32_t par = -1;
                 int32_t pos = 0;   // position of the hit in the row
-                // entries the head probes; with HUB = 2 its last word holds ranks
-                constexpr int32_t nprobe = HUB >= 2 ? 2 : 3;
                 if (HUB >= 2) {
-                    const uint32_t r0 = (uint32_t)h.w & 0xFFFFu, r1 = (uint32_t)h.w >> 16;
-                    // both probes are issued before either is tested
-                    const uint64_t f0 = deg > 0 ? (r0 != 0xFFFFu ? s_hb[r0 >> 6] : fbits[h.y >> 6]) : 0ull;
-                    const uint64_t f1 = deg > 1 ? (r1 != 0xFFFFu ? s_hb[r1 >> 6] : fbits[h.z >> 6]) : 0ull;
-                    if (deg > 0 && bit_of(f0, r0 != 0xFFFFu ? (int32_t)r0 : h.y)) { par = h.y; pos = 0; }
-                    else if (deg > 1 && bit_of(f1, r1 != 0xFFFFu ? (int32_t)r1 : h.z)) { par = h.z; pos = 1; }
+                    const uint32_t q0 = (uint32_t)h.w & 0xFFFFu, q1 = (uint32_t)h.w >> 16;
+                    if (deg > 0 && bit_of(fa[j], q0 != 0xFFFFu ? (int32_t)q0 : h.y)) { par = h.y; pos = 0; }
+                    else if (deg > 1 && bit_of(fb[j], q1 != 0xFFFFu ? (int32_t)q1 : h.z)) { par = h.z; pos = 1; }
                 } else {
-                    if (deg > 0 && bit_of(fbits[h.y >> 6], h.y)) { par = h.y; pos = 0; }
+                    if (deg > 0 && bit_of(fa[j], h.y)) { par = h.y; pos = 0; }
                     else if (deg > 1 && bit_of(fbits[h.z >> 6], h.z)) { par = h.z; pos = 1; }
                     else if (deg > 2 && bit_of(fbits[h.w >> 6], h.w)) { par = h.w; pos = 2; }
                 }
@@ -218,8 +242,9 @@ __device__ __forceinline__ void bu_sweep_body(
                 if (!cont) {
                     if (par >= 0) found(v, par, pos, deg);
                     else if (act) my_x += (uint64_t)(deg > nprobe ? pbase + deg : deg);
-                    // the entry's result replaces its head index (read one round ago)
+                    // the entry's result replaces its head index (read already)
                     if (FILL && act) hlist[r + lane] = par;
+                }
                 }
             }
             wave_lds_sync();

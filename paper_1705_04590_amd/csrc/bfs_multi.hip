@@ -30,6 +30,7 @@ enum { M_QLEN = 0, M_NNEXT = 1, M_MNEXT = 2, M_OR = 3, M_MFULL = 4, M_EXAM = 5, 
 // come from the frontier side instead (k_ms_hub_resolve)
 constexpr int64_t MS_HUB_ROW = 512;
 constexpr int MS_ROWS_BLOCK = 256;
+constexpr int MS_STEP = 4;   // row entries a lane loads at once in the supplier scan
 
 // Workgroup totals added once per workgroup to its line of the slot (sums;
 // the OR of the new-source bits; the maximum row length `mx`).  Every word is
@@ -285,18 +286,18 @@ __device__ __forceinline__ uint64_t first_suppliers(const int32_t* __restrict__ 
     uint64_t found = 0;
     int64_t p = beg;
     const int64_t lim = (end - beg > serial) ? beg + serial : end;
-    // four entries per step: their column loads, then their mask loads, all
-    // independent; then taken in row order, stopping right after the entry
-    // that supplies the last needed source
+    // MS_STEP entries per step: their column loads, then their mask loads,
+    // all independent; then taken in row order, stopping right after the
+    // entry that supplies the last needed source
     while (need && p < lim) {
-        int32_t u[4];
-        uint64_t f[4];
+        int32_t u[MS_STEP];
+        uint64_t f[MS_STEP];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) u[j] = p + j < lim ? cols[p + j] : -1;
+        for (int j = 0; j < MS_STEP; ++j) u[j] = p + j < lim ? cols[p + j] : -1;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) f[j] = u[j] >= 0 ? F[u[j]] : 0ull;
+        for (int j = 0; j < MS_STEP; ++j) f[j] = u[j] >= 0 ? F[u[j]] : 0ull;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < MS_STEP; ++j) {
             if (need && u[j] >= 0) {
                 const uint64_t x = f[j] & need;
                 if (x) {
