@@ -383,6 +383,271 @@ __global__ __launch_bounds__(BLK, 5) void k_bu_sweep(BFS_SWEEP_PARAMS) {
     bu_sweep_body<OffT, HUB, FILL, SEG, BLK>(BFS_SWEEP_ARGS);
 }
 
+// ---------------------------------------------------------- first sweep
+// The first bottom-up level of a search whose outputs were left unwritten
+// (FILL = 1 of k_bu_sweep), laid out one lane per vertex: a wave takes
+// BF_WORDS consecutive 64-vertex words at once, with no compacted lists, so
+// the loads of all its vertices' heads, and then all their probes, are in
+// flight together.  A lane's vertex: reached earlier (the source among
+// them) -> nothing written; isolated -> -1; otherwise its head is probed (HUB
+// as in k_bu_sweep), and its parent and depth, or -1, are written with its
+// word: lanes write consecutive entries, so each output line is written once,
+// whole but for entries of vertices reached earlier.  A vertex whose row goes
+// on past an unsettled head (about one in a hundred on a large level) joins
+// its wave's waiting list, and the list's rows are scanned a full wave (64)
+// at a time (k_bu_sweep's second pass), so a step does not wait for one
+// lane's chain of offset, column and probe loads.  A hit found there is
+// written over the entry's -1.  Counts and bitmaps as k_bu_sweep.
+constexpr int BF_WORDS = 8;
+
+// lane j's value of x (j the same in every lane), as a wave-uniform value
+__device__ __forceinline__ uint64_t read_lane64(uint64_t x, int j) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// v's row, entries [from, deg) at cols + beg: the first frontier entry. A lane
+// with `need` scans alone for `serial_len` entries, four loads at a time; the
+// rows left are then scanned by the whole wave, one at a time (every lane of
+// the wave calls this).  Returns the entry (-1 if none); *at = its position.
+__device__ __forceinline__ int32_t row_first_hit(const int32_t* __restrict__ cols, const uint64_t* __restrict__ fbits,
+                                                 int64_t beg, int32_t deg, int32_t from, bool need, int serial_len,
+                                                 int32_t* at) {
+    const int lane = lane_id();
+    int32_t par = -1, rp = deg;
+    if (need) {
+        const int32_t lim = deg - from > serial_len ? from + serial_len : deg;
+        const int32_t* row = cols + beg;
+        for (rp = from; rp < lim; rp += 4) {
+            const int32_t c0 = row[rp];
+            const int32_t c1 = rp + 1 < lim ? row[rp + 1] : -1;
+            const int32_t c2 = rp + 2 < lim ? row[rp + 2] : -1;
+            const int32_t c3 = rp + 3 < lim ? row[rp + 3] : -1;
+            const uint64_t f0 = fbits[c0 >> 6];
+            const uint64_t f1 = c1 >= 0 ? fbits[c1 >> 6] : 0ull;
+            const uint64_t f2 = c2 >= 0 ? fbits[c2 >> 6] : 0ull;
+            const uint64_t f3 = c3 >= 0 ? fbits[c3 >> 6] : 0ull;
+            if (bit_of(f0, c0)) { par = c0; break; }
+            if (c1 >= 0 && bit_of(f1, c1)) { par = c1; rp += 1; break; }
+            if (c2 >= 0 && bit_of(f2, c2)) { par = c2; rp += 2; break; }
+            if (c3 >= 0 && bit_of(f3, c3)) { par = c3; rp += 3; break; }
+        }
+        if (par < 0 && rp > lim) rp = lim;
+    }
+    uint64_t rem = __ballot(need && par < 0 && rp < deg);
+    while (rem) {
+        const int l = __ffsll((unsigned long long)rem) - 1;
+        rem &= rem - 1;
+        const int32_t* row = cols + __shfl(beg, l, WAVE);
+        const int32_t pb = __shfl(rp, l, WAVE);
+        const int32_t pe = __shfl(deg, l, WAVE);
+        int32_t got = -1, gotpos = pe;
+        for (int32_t b = pb; b < pe; b += WAVE) {
+            const int32_t i = b + lane;
+            bool hit = false;
+            int32_t c = 0;
+            if (i < pe) {
+                c = row[i];
+                hit = bit_of(fbits[c >> 6], c);
+            }
+            const uint64_t hm = __ballot(hit);
+            if (hm) {
+                const int f = __ffsll((unsigned long long)hm) - 1;
+                got = __shfl(c, f, WAVE);
+                gotpos = b + f;
+                break;
+            }
+        }
+        if (lane == l) {
+            par = got;
+            rp = gotpos;
+        }
+    }
+    *at = rp;
+    return par;
+}
+
+template <typename OffT, int HUB>
+__global__ __launch_bounds__(BU_BLOCK) void k_bu_fill(
+    const int4* __restrict__ head, const uint64_t* __restrict__ iso, const uint32_t* __restrict__ nbase,
+    const OffT* __restrict__ off, const int32_t* __restrict__ cols, const uint64_t* __restrict__ fbits,
+    const uint64_t* __restrict__ hb, uint64_t* __restrict__ nbits, uint64_t* __restrict__ visited,
+    uint64_t* __restrict__ vprev, int32_t* __restrict__ parent, int32_t* __restrict__ depth, int64_t W,
+    int32_t next_depth, int serial_len, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot, int64_t n,
+    int64_t src) {
+    __shared__ uint64_t s_hb[HUB >= 2 ? HUB_BITS / 64 : 1];
+    // vertices whose head did not settle them, waiting for their row scan
+    __shared__ int32_t s_miss[BU_BLOCK / WAVE][WAVE * (BF_WORDS + 1)];
+    if (HUB >= 2) {
+        for (int i = threadIdx.x; i < HUB_BITS / 64; i += BU_BLOCK) s_hb[i] = hb[i];
+        __syncthreads();
+    }
+    zero_slot(zslot);
+    const int lane = lane_id();
+    const uint64_t lbit = 1ull << lane;
+    int32_t* miss = s_miss[threadIdx.x / WAVE];
+    int nmiss = 0;   // wave-uniform
+    const int64_t G = (W + BF_WORDS - 1) / BF_WORDS;
+    const int64_t nwaves = (int64_t)gridDim.x * (BU_BLOCK / WAVE);
+    uint64_t my_n = 0, my_m = 0, my_x = 0;
+    // entries the head probes; with HUB = 2 its last word holds hub ranks
+    constexpr int32_t nprobe = HUB >= 2 ? 2 : 3;
+    // a row scan starts past the head when the head is the row's prefix;
+    // positions count the head's probes too when it is not
+    constexpr int32_t skip = HUB ? 0 : 3, pbase = HUB ? nprobe : 0;
+    // the row scans of `cnt` (<= 64) waiting vertices from list index i0, one per lane.
+    // Their entries hold -1 already (written with their word); a hit
+    // overwrites them and sets the vertex's bits with atomics.  The release
+    // fence first completes this wave's earlier stores to the same words and
+    // entries.
+    auto drain = [&](int i0, int cnt) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        const bool a = lane < cnt;
+        const int32_t v = a ? miss[i0 + lane] : 0;
+        int64_t beg = 0;
+        int32_t deg = 0;
+        if (a) {
+            beg = (int64_t)off[v];
+            deg = (int32_t)((int64_t)off[v + 1] - beg);
+        }
+        int32_t at = 0;
+        const int32_t got = row_first_hit(cols, fbits, beg, deg, skip, a, serial_len, &at);
+        if (a) {
+            if (got >= 0) {
+                my_n += 1;
+                my_m += (uint64_t)deg;
+                my_x += (uint64_t)(pbase + at + 1);
+                __builtin_nontemporal_store(got, &parent[v]);
+                __builtin_nontemporal_store(next_depth, &depth[v]);
+                const unsigned long long bit = 1ull << (v & 63);
+                atomicOr((unsigned long long*)&nbits[v >> 6], bit);
+                atomicOr((unsigned long long*)&visited[v >> 6], bit);
+                atomicOr((unsigned long long*)&vprev[v >> 6], bit);
+            } else {
+                my_x += (uint64_t)(pbase + deg);
+            }
+        }
+    };
+    // lane j < BF_WORDS holds word j of the wave's current step; the next
+    // step's words are loaded while the current one is processed
+    int64_t gi = (int64_t)blockIdx.x * (BU_BLOCK / WAVE) + threadIdx.x / WAVE;
+    uint64_t cv = ~0ull, ci = ~0ull;
+    uint32_t cb = 0;
+    if (gi < G && lane < BF_WORDS && gi * BF_WORDS + lane < W) {
+        const int64_t w = gi * BF_WORDS + lane;
+        cv = stream_load(&visited[w]);
+        ci = stream_load(&iso[w]);
+        cb = nbase[w];
+    }
+    for (; gi < G; gi += nwaves) {
+        const int64_t w0 = gi * BF_WORDS;
+        uint64_t vw[BF_WORDS], iw[BF_WORDS];
+        uint32_t base[BF_WORDS];
+#pragma unroll
+        for (int j = 0; j < BF_WORDS; ++j) {
+            vw[j] = read_lane64(cv, j);
+            iw[j] = read_lane64(ci, j);
+            base[j] = (uint32_t)__builtin_amdgcn_readlane((int)cb, j);
+        }
+        {
+            const int64_t gn = gi + nwaves;
+            cv = ~0ull;
+            ci = ~0ull;
+            cb = 0;
+            if (gn < G && lane < BF_WORDS && gn * BF_WORDS + lane < W) {
+                const int64_t w = gn * BF_WORDS + lane;
+                cv = stream_load(&visited[w]);
+                ci = stream_load(&iso[w]);
+                cb = nbase[w];
+            }
+        }
+        // this lane's vertices: unvisited with edges load their heads
+        bool act[BF_WORDS];
+        int4 h[BF_WORDS];
+#pragma unroll
+        for (int j = 0; j < BF_WORDS; ++j) {
+            act[j] = !((vw[j] | iw[j]) & lbit);
+            h[j] = make_int4(0, -1, -1, -1);
+            if (act[j]) h[j] = stream_load4(&head[base[j] + (uint32_t)__popcll(~iw[j] & (lbit - 1ull))]);
+        }
+        uint64_t fa[BF_WORDS], fb[BF_WORDS];
+#pragma unroll
+        for (int j = 0; j < BF_WORDS; ++j) {
+            const int deg = h[j].x;
+            if (HUB >= 2) {
+                const uint32_t q0 = (uint32_t)h[j].w & 0xFFFFu, q1 = (uint32_t)h[j].w >> 16;
+                fa[j] = deg > 0 ? (q0 != 0xFFFFu ? s_hb[q0 >> 6] : fbits[h[j].y >> 6]) : 0ull;
+                fb[j] = deg > 1 ? (q1 != 0xFFFFu ? s_hb[q1 >> 6] : fbits[h[j].z >> 6]) : 0ull;
+            } else {
+                fa[j] = deg > 0 ? fbits[h[j].y >> 6] : 0ull;
+                fb[j] = 0ull;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < BF_WORDS; ++j) {
+            const int64_t w = w0 + j;
+            const int64_t v = w * WAVE + lane;
+            const int32_t deg = h[j].x;
+            int32_t par = -1, pos = 0;
+            if (HUB >= 2) {
+                const uint32_t q0 = (uint32_t)h[j].w & 0xFFFFu, q1 = (uint32_t)h[j].w >> 16;
+                if (deg > 0 && bit_of(fa[j], q0 != 0xFFFFu ? (int32_t)q0 : h[j].y)) { par = h[j].y; pos = 0; }
+                else if (deg > 1 && bit_of(fb[j], q1 != 0xFFFFu ? (int32_t)q1 : h[j].z)) { par = h[j].z; pos = 1; }
+            } else {
+                if (deg > 0 && bit_of(fa[j], h[j].y)) { par = h[j].y; pos = 0; }
+                else if (deg > 1 && bit_of(fbits[h[j].z >> 6], h[j].z)) { par = h[j].z; pos = 1; }
+                else if (deg > 2 && bit_of(fbits[h[j].w >> 6], h[j].w)) { par = h[j].w; pos = 2; }
+            }
+            const bool found = par >= 0;
+            // the head did not settle v and its row goes on: the scan waits
+            const bool cont = act[j] && !found && deg > nprobe;
+            const uint64_t cm = __ballot(cont);
+            if (cont) miss[nmiss + __popcll(cm & lanemask_lt())] = (int32_t)v;
+            nmiss += __popcll(cm);
+            if (found) {
+                my_n += 1;
+                my_m += (uint64_t)deg;
+                my_x += (uint64_t)(pos + 1);
+            } else if (act[j] && !cont) {
+                my_x += (uint64_t)deg;
+            }
+            // every entry of a vertex not reached before this level, once
+            // (isolated vertices are marked visited when a search starts)
+            const bool unreached = !(vw[j] & lbit) || ((iw[j] & lbit) && v != src);
+            if (v < n && unreached) {
+                parent[v] = found ? par : -1;
+                depth[v] = found ? next_depth : -1;
+            }
+            const uint64_t nb = __ballot(found);
+            if (lane == 0 && w < W) {
+                nbits[w] = nb;
+                if (nb) {
+                    visited[w] = vw[j] | nb;
+                    vprev[w] = vw[j] | nb;
+                }
+            }
+        }
+        // full waves of waiting rows are scanned; the rest move to the front
+        if (nmiss >= WAVE) {
+            wave_lds_sync();
+            int done = 0;
+            for (; nmiss - done >= WAVE; done += WAVE) drain(done, WAVE);
+            const int rest = nmiss - done;
+            int32_t keep = lane < rest ? miss[done + lane] : 0;
+            wave_lds_sync();
+            if (lane < rest) miss[lane] = keep;
+            nmiss = rest;
+        }
+    }
+    if (nmiss) {
+        wave_lds_sync();
+        drain(0, nmiss);
+    }
+    uint64_t* ln = slot_line(slot);
+    block_add3<BU_BLOCK / WAVE>(my_n, my_m, my_x, &ln[S_NNEXT], &ln[S_MNEXT], &ln[S_EXAMINED]);
+}
+
 // the hub pre-pass of a heavy top-down level (a kernel of its own name, so
 // profiles keep it apart from the bottom-up step)
 template <typename OffT, int FILL>
@@ -566,6 +831,20 @@ void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t*
     if (blk == 128) { BFS_SWEEP_H(F, 0, 128) }            \
     else if (blk == 512) { BFS_SWEEP_H(F, 0, 512) }       \
     else { BFS_SWEEP_H(F, 0, BU_BLOCK) }
+    if (fill && (hub == 1 || hub == 2) && !pend) {
+        // the first sweep of a search that writes the outputs, with heads of
+        // high-degree neighbours: one lane per vertex.  Heads that are row
+        // prefixes (HUB = 0) leave far more rows to scan (about one vertex in
+        // five on a large level), and k_bu_sweep's compacted lists do better.
+        const int gf = grid_for((W + BF_WORDS - 1) / BF_WORDS, BU_BLOCK / WAVE, L.grid_cap);
+#define BFS_FILL1(H)                                                                                             \
+    hipLaunchKernelGGL((k_bu_fill<OffT, H>), dim3(gf), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off, cols, \
+                       fbits, hb, nbits, visited, vprev, parent, depth, W, next_depth, serial_len, slot, zslot, n, src)
+        if (hub == 2) BFS_FILL1(2);
+        else BFS_FILL1(1);
+#undef BFS_FILL1
+        return;
+    }
     if (hub == 3) {
         if (fill) BFS_PREPASS(1);
         else BFS_PREPASS(0);

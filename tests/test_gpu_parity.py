@@ -136,6 +136,13 @@ def test_parity_all_modes(orc, graphs, name, direction):
                 check(orc, dg, s, p, d, pm == bfs.BFS_PARENT_MIN, ref)
                 assert st.reached == int((d >= 0).sum())
                 assert st.isolated == int((np.diff(dg.off) == 0).sum())
+                # per-level counts depend on the depths only, in every mode
+                n_f, m_f, m_u = orc.level_stats(dg.off, ref[1])
+                L = min(len(n_f), bfs.STATS_MAX_LEVELS)
+                assert st.levels == len(n_f)
+                assert list(st.level_nf[:L]) == n_f[:L].tolist()
+                assert list(st.level_mf[:L]) == m_f[:L].tolist()
+                assert list(st.level_mu[:L]) == m_u[:L].tolist()
 
 
 @pytest.mark.parametrize("name", ["kron12", "kron14", "grid", "pieces"])
