@@ -437,16 +437,13 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
         // the workgroups could not all be resident: level by level instead
     }
 
-    // degree of the source: the first frontier's edge count
+    // degree of the source: the first frontier's edge count.  The
+    // initialisation does not need it and is queued behind the request, so
+    // it runs while the host waits for the answer.
     const uint64_t* h = nullptr;   // the last level's counters, in the mailbox
-    {
-        const uint64_t seq = ++ctx->seq;
-        launch_post_row<OffT>(stream, off, src, ctx->mbox_dev, seq);
-        HIP_TRY(hipGetLastError());
-        bfs_status ws_ = mbox_wait(ctx, stream, seq);
-        if (ws_ != BFS_OK) return ws_;
-    }
-    const int64_t deg_s = (int64_t)ctx->mbox[2] - (int64_t)ctx->mbox[1];
+    const uint64_t row_seq = ++ctx->seq;
+    launch_post_row<OffT>(stream, off, src, ctx->mbox_dev, row_seq);
+    HIP_TRY(hipGetLastError());
 
     // ANY parents with fetch-or claims never read parent/depth, so their -1
     // fill moves into the first bottom-up sweep (whole lines, once), or to a
@@ -461,6 +458,11 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     HIP_TRY(hipGetLastError());
     HIP_TRY(T.end(BFS_K_INIT, -1));
     if (st) st->launches[BFS_K_INIT] += 1;
+    {
+        bfs_status ws_ = mbox_wait(ctx, stream, row_seq);
+        if (ws_ != BFS_OK) return ws_;
+    }
+    const int64_t deg_s = (int64_t)ctx->mbox[2] - (int64_t)ctx->mbox[1];
 
     int64_t n_f = 1, m_f = deg_s, m_u = g->nnz - deg_s;
     int64_t qlen = deg_s > 0 ? 1 : 0;     // exact queue length when qlen_dev is NULL
