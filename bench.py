@@ -654,8 +654,9 @@ def main():
         log(f"[bench] kernel ms over timed steps: " +
             ", ".join(f"{k}={v:.2f}" for k, v in sorted(kernel_totals.items(), key=lambda x: -x[1]) if v))
     if not args.no_timing and table is not None:
-        # events bracket only the bottom-up sweeps (timing mode 2), the
-        # dominant kernel of this workload (see the kernel-trace profile)
+        # events bracket only the bottom-up steps (timing mode 2), the
+        # dominant kernel of this workload (see the kernel-trace profile):
+        # k_bu_fill on a search's first bottom-up level, k_bu_sweep on the others
         dom = "bu_sweep"
         wo = d_off.element_size()
         nbytes, launches, ms = 0.0, 0, 0.0
@@ -672,6 +673,7 @@ def main():
             traffic = read_traffic(dom)
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                        "kernels": "k_bu_fill (first bottom-up level of a search), k_bu_sweep (the others)",
                         "launches": launches, "avg_launch_us": round(avg_s * 1e6, 2),
                         "alg_bytes_per_launch": round(nbytes / launches),
                         "alg_bytes_from": f"oracle work table {table['path']} (counts of the timed sources; "

@@ -81,7 +81,7 @@ enum {
     BFS_K_INIT = 0,        /* output and bitmap initialisation                */
     BFS_K_TD_SCAN = 1,     /* frontier degree prefix sum (top-down)           */
     BFS_K_TD_EXPAND = 2,   /* top-down edge expansion and claims              */
-    BFS_K_BU_SWEEP = 3,    /* bottom-up first-hit sweep                       */
+    BFS_K_BU_SWEEP = 3,    /* bottom-up step (first-hit sweep of a level)     */
     BFS_K_CONVERT = 4,     /* queue <-> bitmap frontier conversions, merges   */
     BFS_K_MS_LEVEL = 5,    /* multi-source level kernel                       */
     BFS_K_MS_OUTPUT = 6,   /* multi-source output kernels                     */
