@@ -3,7 +3,7 @@
 // levels, Alg. 2 bottom-up levels, the Section 4.4 rule applied on the
 // device between them).  A small graph's levels are too short to fill the
 // chip, so a host round trip and a handful of launches per level cost more
-// than the level's work; here a level costs two grid barriers.
+// than the level's work; here a level costs one grid barrier.
 //
 // Both frontiers are bitmaps (n/64 words each).  Level d:
 //   * top-down: each wave takes frontier words; a frontier vertex with a
