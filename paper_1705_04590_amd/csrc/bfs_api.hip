@@ -451,6 +451,14 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
     // modes compare against -1 and need it before the first top-down level
     const bool lazy_out = any_bitmap && o.dir != BFS_DIR_TD && g->d_iso != nullptr;
     bool out_filled = !lazy_out;
+    // Before the outputs are filled, a top-down level's winners (the next
+    // frontier) may leave their depth unwritten: the next level writes it,
+    // with whole lines when it is the sweep that fills the outputs (or the
+    // hub pre-pass that fills them), else from the frontier queue.  Only
+    // fetch-or claims on symmetric graphs, where every winner has an edge and
+    // so enters the queue.
+    const bool defer_depth = lazy_out && claim_mode == CLAIM_BITMAP && (g->flags & BFS_GRAPH_SYMMETRIC);
+    bool depth_pending = false;
     int32_t fill_level = -1;   // reported in stats: who wrote the -1 of the vertices not reached
     HIP_TRY(T.begin(BFS_K_INIT));
     launch_init(L, parent, depth, n, visited, vprev, fbits, claim, g->d_iso, W, qcur, src, counters,
@@ -523,6 +531,14 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             const int rec_cap = (st && level < BFS_STATS_MAX_LEVELS) ? BFS_STATS_MAX_LEVELS - level : 0;
             // forced top-down never switches: with alpha = 0 the rule m_f * alpha > m_u cannot fire
             const double eng_alpha = o.dir == BFS_DIR_TD ? 0.0 : o.alpha;
+            if (depth_pending) {
+                HIP_TRY(T.begin(BFS_K_CONVERT));
+                launch_queue_depth(L, qcur, nullptr, qlen, depth, level);
+                HIP_TRY(hipGetLastError());
+                HIP_TRY(T.end(BFS_K_CONVERT, level));
+                if (st) st->launches[BFS_K_CONVERT] += 1;
+                depth_pending = false;
+            }
             HIP_TRY(T.begin(BFS_K_TD_EXPAND));
             // the engine's small levels keep exact claims in the benign mode
             launch_td_persist<OffT>(L, claim_mode == CLAIM_BENIGN ? CLAIM_BITMAP : claim_mode, groups, off, g->cols, parent, depth, visited, vprev, claim, qcur,
@@ -602,6 +618,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
 
         const int32_t next_depth = level + 1;
         bool prepass = false;
+        bool skipped_depth = false;   // this level's winners left their depth to the next level
         if (cur_dir == 0) {
             if (m_f > 0) {
                 // a heavy top-down level of an any-parent search first lets
@@ -625,7 +642,8 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                     HIP_TRY(T.begin(BFS_K_TD_EXPAND));
                     launch_bu_sweep<OffT>(L, g->d_hubr, 3, g->d_iso, g->d_nbase, off, g->cols, fbits, hb, nbits,
                                           visited, vprev, parent, depth, W, next_depth, serial, slot, zslot,
-                                          !out_filled, n, src);
+                                          !out_filled, n, src, nullptr, 0, 0, depth_pending);
+                    depth_pending = false;
                     if (!out_filled) fill_level = level;
                     out_filled = true;
                     HIP_TRY(hipGetLastError());
@@ -635,6 +653,16 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                 int nl = 0;
                 const int64_t seg_min = o.td_seg_edges > 0 ? o.td_seg_edges : TD_SEG_MIN_EDGES;
                 const int tds = m_f >= seg_min ? o.td_segments : 0;
+                if (depth_pending) {
+                    // the frontier's depths, left by the level before
+                    HIP_TRY(T.begin(BFS_K_CONVERT));
+                    launch_queue_depth(L, qcur, nullptr, qlen, depth, level);
+                    HIP_TRY(hipGetLastError());
+                    HIP_TRY(T.end(BFS_K_CONVERT, level));
+                    if (st) st->launches[BFS_K_CONVERT] += 1;
+                    depth_pending = false;
+                }
+                skipped_depth = defer_depth && !out_filled && tds == 0;
                 if (tds > 0) {
                     // column segments in ascending order: each pass expands
                     // only the frontier's entries inside its id range, so
@@ -663,8 +691,8 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
                     HIP_TRY(T.end(BFS_K_TD_SCAN, level));
                     HIP_TRY(T.begin(BFS_K_TD_EXPAND));
                     launch_td_expand<OffT>(L, claim_mode, off, g->cols, g->nnz, qcur, qlen_dev, qlen, scan, tiles,
-                                           m_f, parent, depth, visited, claim, qnext, slot, zslot, next_depth,
-                                           nullptr, nullptr, o.td_block);
+                                           m_f, parent, skipped_depth ? nullptr : depth, visited, claim, qnext, slot,
+                                           zslot, next_depth, nullptr, nullptr, o.td_block);
                     HIP_TRY(hipGetLastError());
                     HIP_TRY(T.end(BFS_K_TD_EXPAND, level));
                 }
@@ -720,7 +748,8 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             HIP_TRY(T.begin(BFS_K_BU_SWEEP));
             launch_bu_sweep<OffT>(L, hk == 2 ? g->d_hubr : hk == 1 ? g->d_hub : g->d_head, hk, g->d_iso, g->d_nbase,
                                   off, g->cols, fbits, hb, nbits, visited, vprev, parent, depth, W, next_depth, serial,
-                                  slot, zslot, !out_filled, n, src, pend_a, o.bu_block, o.bu_group);
+                                  slot, zslot, !out_filled, n, src, pend_a, o.bu_block, o.bu_group, depth_pending);
+            depth_pending = false;
             if (!out_filled) fill_level = level;
             out_filled = true;
             const int64_t segw = segs ? (W + segs - 1) / segs : 0;
@@ -767,6 +796,7 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
         }
         ++level;
         if (n_next == 0) break;
+        depth_pending = skipped_depth;
         reached += n_next;
         unvisited -= n_next;
         m_u -= m_next;
@@ -786,6 +816,11 @@ bfs_status run_single(bfs_graph* g, int64_t src, const bfs_opts& o, int32_t* par
             uint64_t* t = fbits; fbits = nbits; nbits = t;
         }
         if (level > n + 1) return fail(BFS_E_HIP, "level loop did not terminate");
+    }
+    if (depth_pending) {
+        // not reached: a level with no winners ends the search, and the
+        // winners of the level before had their depth written at its start
+        return fail(BFS_E_HIP, "internal: a frontier's depths were left unwritten");
     }
     if (!out_filled) {
         fill_level = -2;

@@ -91,7 +91,7 @@ __device__ __forceinline__ void bu_sweep_body(
     uint64_t* __restrict__ visited, uint64_t* __restrict__ vprev, int32_t* __restrict__ parent,
     int32_t* __restrict__ depth, int64_t W, int GW,
     int32_t next_depth, int serial_len, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot, int64_t n,
-    int64_t src, uint64_t* __restrict__ pend) {
+    int64_t src, uint64_t* __restrict__ pend, int frontier_depth) {
     __shared__ int32_t s_list[BLK / WAVE][BU_WIN];
     __shared__ int32_t s_hidx[BLK / WAVE][BU_WIN];
     __shared__ unsigned long long s_nb[BLK / WAVE][WAVE];
@@ -132,6 +132,8 @@ __device__ __forceinline__ void bu_sweep_body(
         const uint64_t wv = mine ? stream_load(&visited[w]) : ~0ull;
         // head records exist for vertices with edges only: index = rank among them
         const uint64_t hasrow = mine ? ~stream_load(&iso[w]) : 0ull;
+        // frontier vertices whose depth the fill writes (frontier_depth)
+        const uint64_t fdw = FILL && frontier_depth && mine ? fbits[w] : 0ull;
         const uint32_t hbase = mine ? nbase[w] : 0u;
         const int cnt = __popcll(~wv);
         const int incl = wave_incl_scan(cnt);
@@ -344,6 +346,7 @@ __device__ __forceinline__ void bu_sweep_body(
                 if (wj >= W) break;
                 const uint64_t unv = ~__shfl(wv, j, WAVE);
                 uint64_t iso_j = ~__shfl(hasrow, j, WAVE);
+                const uint64_t fd_j = __shfl(fdw, j, WAVE);
                 const int base = __shfl(first, j, WAVE);
                 if (wj == W - 1 && (n & 63)) iso_j &= (1ull << (n & 63)) - 1ull;
                 if (wj == (src >> 6)) iso_j &= ~(1ull << (src & 63));
@@ -356,6 +359,8 @@ __device__ __forceinline__ void bu_sweep_body(
                 } else if (iso_j & bit) {
                     parent[v] = -1;
                     depth[v] = -1;
+                } else if (fd_j & bit) {
+                    depth[v] = next_depth - 1;
                 }
             }
         }
@@ -371,10 +376,10 @@ __device__ __forceinline__ void bu_sweep_body(
         const uint64_t* __restrict__ hb, uint64_t* __restrict__ nbits, uint64_t* __restrict__ visited,             \
         uint64_t* __restrict__ vprev, int32_t* __restrict__ parent, int32_t* __restrict__ depth, int64_t W, int GW, \
         int32_t next_depth, int serial_len, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot, int64_t n,  \
-        int64_t src, uint64_t* __restrict__ pend
+        int64_t src, uint64_t* __restrict__ pend, int frontier_depth
 #define BFS_SWEEP_ARGS                                                                                            \
     head, iso, nbase, off, cols, fbits, hb, nbits, visited, vprev, parent, depth, W, GW, next_depth, serial_len,   \
-        slot, zslot, n, src, pend
+        slot, zslot, n, src, pend, frontier_depth
 
 // the bottom-up step
 // (BLK threads per workgroup, one 64-lane wave per group of words)
@@ -475,7 +480,7 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_fill(
     const uint64_t* __restrict__ hb, uint64_t* __restrict__ nbits, uint64_t* __restrict__ visited,
     uint64_t* __restrict__ vprev, int32_t* __restrict__ parent, int32_t* __restrict__ depth, int64_t W,
     int32_t next_depth, int serial_len, uint64_t* __restrict__ slot, uint64_t* __restrict__ zslot, int64_t n,
-    int64_t src) {
+    int64_t src, int frontier_depth) {
     __shared__ uint64_t s_hb[HUB >= 2 ? HUB_BITS / 64 : 1];
     // vertices whose head did not settle them, waiting for their row scan
     __shared__ int32_t s_miss[BU_BLOCK / WAVE][WAVE * (BF_WORDS + 1)];
@@ -532,34 +537,38 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_fill(
     // lane j < BF_WORDS holds word j of the wave's current step; the next
     // step's words are loaded while the current one is processed
     int64_t gi = (int64_t)blockIdx.x * (BU_BLOCK / WAVE) + threadIdx.x / WAVE;
-    uint64_t cv = ~0ull, ci = ~0ull;
+    uint64_t cv = ~0ull, ci = ~0ull, cf = 0ull;
     uint32_t cb = 0;
     if (gi < G && lane < BF_WORDS && gi * BF_WORDS + lane < W) {
         const int64_t w = gi * BF_WORDS + lane;
         cv = stream_load(&visited[w]);
         ci = stream_load(&iso[w]);
         cb = nbase[w];
+        if (frontier_depth) cf = fbits[w];
     }
     for (; gi < G; gi += nwaves) {
         const int64_t w0 = gi * BF_WORDS;
-        uint64_t vw[BF_WORDS], iw[BF_WORDS];
+        uint64_t vw[BF_WORDS], iw[BF_WORDS], fw[BF_WORDS];
         uint32_t base[BF_WORDS];
 #pragma unroll
         for (int j = 0; j < BF_WORDS; ++j) {
             vw[j] = read_lane64(cv, j);
             iw[j] = read_lane64(ci, j);
+            fw[j] = read_lane64(cf, j);
             base[j] = (uint32_t)__builtin_amdgcn_readlane((int)cb, j);
         }
         {
             const int64_t gn = gi + nwaves;
             cv = ~0ull;
             ci = ~0ull;
+            cf = 0ull;
             cb = 0;
             if (gn < G && lane < BF_WORDS && gn * BF_WORDS + lane < W) {
                 const int64_t w = gn * BF_WORDS + lane;
                 cv = stream_load(&visited[w]);
                 ci = stream_load(&iso[w]);
                 cb = nbase[w];
+                if (frontier_depth) cf = fbits[w];
             }
         }
         // this lane's vertices: unvisited with edges load their heads
@@ -618,6 +627,9 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_fill(
             if (v < n && unreached) {
                 parent[v] = found ? par : -1;
                 depth[v] = found ? next_depth : -1;
+            } else if (fw[j] & lbit) {
+                // reached by the top-down level before, which left its depth
+                depth[v] = next_depth - 1;
             }
             const uint64_t nb = __ballot(found);
             if (lane == 0 && w < W) {
@@ -807,7 +819,7 @@ void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t*
                      const OffT* off, const int32_t* cols, const uint64_t* fbits, const uint64_t* hb, uint64_t* nbits,
                      uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W,
                      int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot, bool fill, int64_t n,
-                     int64_t src, uint64_t* pend, int block, int group_cap) {
+                     int64_t src, uint64_t* pend, int block, int group_cap, bool frontier_depth) {
     // the column-blocked sweep and the pre-pass keep the default shape
     const int blk = (hub == 3 || pend || (block != 128 && block != 512)) ? BU_BLOCK : block;
     int gw = group_words(W, L.grid_cap * (blk / WAVE));
@@ -818,11 +830,11 @@ void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t*
 #define BFS_SWEEP(H, F, S, B)                                                                                     \
     hipLaunchKernelGGL((k_bu_sweep<OffT, H, F, S, B>), dim3(g), dim3(B), 0, L.stream, head, iso, nbase, off,       \
                        cols, fbits, hb, nbits, visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot,  \
-                       zslot, n, src, pend)
+                       zslot, n, src, pend, (int)frontier_depth)
 #define BFS_PREPASS(F)                                                                                              \
     hipLaunchKernelGGL((k_td_hub_prepass<OffT, F>), dim3(g), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off,    \
                        cols, fbits, hb, nbits, visited, vprev, parent, depth, W, gw, next_depth, serial_len, slot,     \
-                       zslot, n, src, pend)
+                       zslot, n, src, pend, (int)frontier_depth)
 #define BFS_SWEEP_H(F, S, B)                 \
     if (hub == 2) BFS_SWEEP(2, F, S, B);     \
     else if (hub == 1) BFS_SWEEP(1, F, S, B); \
@@ -839,7 +851,8 @@ void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t*
         const int gf = grid_for((W + BF_WORDS - 1) / BF_WORDS, BU_BLOCK / WAVE, L.grid_cap);
 #define BFS_FILL1(H)                                                                                             \
     hipLaunchKernelGGL((k_bu_fill<OffT, H>), dim3(gf), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off, cols, \
-                       fbits, hb, nbits, visited, vprev, parent, depth, W, next_depth, serial_len, slot, zslot, n, src)
+                       fbits, hb, nbits, visited, vprev, parent, depth, W, next_depth, serial_len, slot, zslot, n,   \
+                       src, (int)frontier_depth)
         if (hub == 2) BFS_FILL1(2);
         else BFS_FILL1(1);
 #undef BFS_FILL1
@@ -1073,7 +1086,7 @@ void launch_hub_gather(const Launch& L, const uint64_t* fbits, const int32_t* hu
     template void launch_bu_sweep<T>(const Launch&, const int4*, int, const uint64_t*, const uint32_t*,          \
                                      const T*, const int32_t*, const uint64_t*, const uint64_t*, uint64_t*,      \
                                      uint64_t*, uint64_t*, int32_t*, int32_t*, int64_t, int32_t, int, uint64_t*, \
-                                     uint64_t*, bool, int64_t, int64_t, uint64_t*, int, int);                    \
+                                     uint64_t*, bool, int64_t, int64_t, uint64_t*, int, int, bool);              \
     template void launch_bu_segment<T>(const Launch&, const T*, const int32_t*, const uint64_t*, const uint64_t*, \
                                        const uint64_t*, uint64_t*, uint64_t*, int64_t, int32_t*, int32_t*,       \
                                        uint64_t*, uint64_t*, uint64_t*, int32_t, int, uint64_t*);                \

@@ -82,6 +82,9 @@ void launch_init(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, ui
 // parent = depth = -1 for every vertex not reached (the source excepted)
 void launch_fill_unreached(const Launch& L, int32_t* parent, int32_t* depth, int64_t n, const uint64_t* visited,
                            const uint64_t* iso, int64_t src);
+// depth[q[i]] = d for every entry of a queue (qlen_dev, if given, holds its length)
+void launch_queue_depth(const Launch& L, const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host,
+                        int32_t* depth, int32_t d);
 
 // degree prefix sum of the frontier queue + tile partition for the expand
 // (scan[i] = sum of degrees of q[0..i), tile_start[t] = queue index owning
@@ -96,7 +99,8 @@ int launch_td_scan(const Launch& L, const OffT* off, const int32_t* q, const uin
 // total_dev (may be NULL): the edge count on the device (total then bounds
 // the grid); segpos (may be NULL): per queue entry, the row position where
 // its edges start (a column segment's first entry); block: threads per
-// workgroup (128, 512; anything else = TD_BLOCK), the tile stays TD_TILE edges
+// workgroup (128, 512; anything else = TD_BLOCK), the tile stays TD_TILE edges.
+// depth may be NULL: the winners' depths are then not written (see the caller)
 template <typename OffT>
 void launch_td_expand(const Launch& L, int mode, const OffT* off, const int32_t* cols, int64_t nnz,
                       const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host, const int64_t* scan,
@@ -120,13 +124,17 @@ int launch_td_scan_seg(const Launch& L, const OffT* off, const int32_t* cols, co
 // pend (may be NULL): column-blocked level; rows that need scanning past
 // their head are appended to pend (count in slot[S_PEND0]) for the sub-steps.
 // block: threads per workgroup (128, 512; anything else = BU_BLOCK);
-// group_cap > 0 caps the 64-vertex words per wave's work unit
+// group_cap > 0 caps the 64-vertex words per wave's work unit.
+// frontier_depth (with fill): the frontier's vertices were reached by a
+// top-down level that left their depth unwritten; the sweep writes it
+// (next_depth - 1) with the fill
 template <typename OffT>
 void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t* iso, const uint32_t* nbase,
                      const OffT* off, const int32_t* cols, const uint64_t* fbits, const uint64_t* hb, uint64_t* nbits,
                      uint64_t* visited, uint64_t* vprev, int32_t* parent, int32_t* depth, int64_t W,
                      int32_t next_depth, int serial_len, uint64_t* slot, uint64_t* zslot, bool fill, int64_t n,
-                     int64_t src, uint64_t* pend = nullptr, int block = 0, int group_cap = 0);
+                     int64_t src, uint64_t* pend = nullptr, int block = 0, int group_cap = 0,
+                     bool frontier_depth = false);
 // one column-segment sub-step: pending rows (count *cin) scanned over their
 // entries < seg_end; rows that reach a later segment go to pout (count *cout)
 template <typename OffT>

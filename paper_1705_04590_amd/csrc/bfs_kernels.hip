@@ -123,6 +123,22 @@ void launch_fill_unreached(const Launch& L, int32_t* parent, int32_t* depth, int
                        n, visited, iso, src);
 }
 
+// depth[q[i]] = d for the qlen entries of a queue (length on the device when
+// qlen_dev is given)
+__global__ void k_queue_depth(const int32_t* __restrict__ q, const uint64_t* __restrict__ qlen_dev, int64_t qlen_host,
+                              int32_t* __restrict__ depth, int32_t d) {
+    const int64_t qlen = len_of(qlen_dev, qlen_host);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < qlen; i += stride)
+        __builtin_nontemporal_store(d, &depth[q[i]]);
+}
+
+void launch_queue_depth(const Launch& L, const int32_t* q, const uint64_t* qlen_dev, int64_t qlen_host,
+                        int32_t* depth, int32_t d) {
+    hipLaunchKernelGGL(k_queue_depth, dim3(grid_for(qlen_host > 0 ? qlen_host : 1, 256, L.grid_cap)), dim3(256), 0,
+                       L.stream, q, qlen_dev, qlen_host, depth, d);
+}
+
 // ------------------------------------------------------------------ host mailbox
 // Copies nw words to a coherent pinned host buffer and then publishes `seq`
 // in its word 0 (system-scope release after a system-scope fence), so the
@@ -371,8 +387,11 @@ __global__ __launch_bounds__(BLK) void k_td_expand(
             if (won[k]) {
                 // a winner's entries are scattered single words: stored
                 // non-temporally, they cost less than partial lines left dirty
-                // in the L2 for a later write-back
-                __builtin_nontemporal_store(next_depth, &depth[v]);
+                // in the L2 for a later write-back.  Without `depth` the
+                // level's depths are written later, with whole lines (the
+                // next level is the sweep that writes the outputs) or from
+                // the next frontier's queue.
+                if (depth) __builtin_nontemporal_store(next_depth, &depth[v]);
                 dv = (int64_t)off[v + 1] - (int64_t)off[v];
                 my_n += 1;
                 my_m += (uint64_t)dv;
