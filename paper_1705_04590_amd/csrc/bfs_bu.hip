@@ -77,7 +77,9 @@ __device__ __forceinline__ int4 stream_load4(const int4* p) {
 // earlier), and after the group one pass per 64-vertex word writes the
 // word's entries with 64 consecutive stores, so each output line is written
 // by one instruction instead of once by the scattered hit stores and again
-// by a fill pass.  Groups are then at most FILL_GW words, so the whole group
+// by a fill pass.  With frontier_depth the frontier's vertices, reached by
+// the top-down level before, which left their depth unwritten, get it there
+// too.  Groups are then at most FILL_GW words, so the whole group
 // fits one list window.
 // SEG = 1 (column-blocked sweep): the rows are not scanned past their head
 // here; a vertex that still needs its row is appended to the pending list
@@ -394,10 +396,11 @@ __global__ __launch_bounds__(BLK, 5) void k_bu_sweep(BFS_SWEEP_PARAMS) {
 // BF_WORDS consecutive 64-vertex words at once, with no compacted lists, so
 // the loads of all its vertices' heads, and then all their probes, are in
 // flight together.  A lane's vertex: reached earlier (the source among
-// them) -> nothing written; isolated -> -1; otherwise its head is probed (HUB
-// as in k_bu_sweep), and its parent and depth, or -1, are written with its
-// word: lanes write consecutive entries, so each output line is written once,
-// whole but for entries of vertices reached earlier.  A vertex whose row goes
+// them) -> nothing written, except the depth of a frontier vertex when the
+// top-down level before left it (frontier_depth); isolated -> -1; otherwise
+// its head is probed (HUB as in k_bu_sweep), and its parent and depth, or -1,
+// are written with its word: lanes write consecutive entries, so each output
+// line is written once, whole but for entries of vertices reached earlier.  A vertex whose row goes
 // on past an unsettled head (about one in a hundred on a large level) joins
 // its wave's waiting list, and the list's rows are scanned a full wave (64)
 // at a time (k_bu_sweep's second pass), so a step does not wait for one
