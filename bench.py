@@ -296,12 +296,13 @@ def serve_measure(graphs, rates, seconds, max_requests, slots, budget_gib):
         batched = run(t, gi, src, slots, 64)
         rows.append({"rate_x_single_capacity": f, "offered_qps": round(rate, 1), "requests": mr,
                      "batched": {k: round(batched[k], 2) for k in ("queries_per_s", "p50_us", "p99_us",
-                                                                    "mean_batch", "max_inflight")},
+                                                                    "mean_batch", "max_inflight",
+                                                                    "device_max_overlap")},
                      "one_query_per_launch": {k: round(single[k], 2) for k in ("queries_per_s", "p50_us",
                                                                                 "p99_us")}})
         log(f"[serve] {f:>4}x: batched {batched['queries_per_s']:.0f} q/s p50 {batched['p50_us'] / 1e3:.2f} ms "
             f"p99 {batched['p99_us'] / 1e3:.2f} ms (batch {batched['mean_batch']:.1f}, inflight "
-            f"{batched['max_inflight']})")
+            f"{batched['max_inflight']}, overlapping on the device {batched['device_max_overlap']})")
     return cap1, capb, rows
 
 

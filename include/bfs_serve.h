@@ -54,6 +54,10 @@ typedef struct {
     double p50_us, p99_us, mean_us, max_us;   /* latency over completed queries           */
     double first_arrival_s, last_completion_s; /* seconds on the server's clock          */
     double queries_per_s;        /* completed / (last completion - first arrival)        */
+    int64_t device_max_overlap;  /* most batches whose spans on the device overlap: a
+                                    batch's span runs from a HIP event recorded on its
+                                    slot's stream before its first kernel to one after
+                                    its last                                           */
 } bfs_server_stats;
 
 /* Fill *o with defaults: 4 slots, batches of 64, depths only, 8 GiB budget,

@@ -104,6 +104,11 @@ struct bfs_server {
     int64_t submitted = 0, completed = 0, failed = 0, batches = 0, inflight = 0, max_inflight = 0;
     double first_arrival = -1.0, last_completion = 0.0;
     std::vector<Rec> recs;
+    // every batch's span on the device: HIP events recorded on its slot's
+    // stream before its first and after its last kernel, in ms after `ref_ev`
+    // (recorded once when the server starts)
+    hipEvent_t ref_ev = nullptr;
+    std::vector<std::pair<double, double>> dev_spans;
     bfs_status first_error = BFS_OK;
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
@@ -171,6 +176,12 @@ struct bfs_server {
         (void)hipSetDevice(device);
         hipStream_t stream = nullptr;
         if (hipStreamCreate(&stream) != hipSuccess) return;
+        hipEvent_t ev_a = nullptr, ev_b = nullptr;
+        if (hipEventCreate(&ev_a) != hipSuccess || hipEventCreate(&ev_b) != hipSuccess) {
+            if (ev_a) (void)hipEventDestroy(ev_a);
+            (void)hipStreamDestroy(stream);
+            return;
+        }
         std::vector<Req> batch;
         std::vector<int64_t> srcs;
         for (;;) {
@@ -189,6 +200,7 @@ struct bfs_server {
             int32_t* depth = (int32_t*)(chunk + Pool::round(ws_bytes));
             int32_t* parent = (o.want_parent || k == 1) ? depth + (size_t)k * (size_t)n : nullptr;
             bfs_status st;
+            const bool span_a = hipEventRecord(ev_a, stream) == hipSuccess;
             if (k == 1) {
                 bfs_opts so = o.opts;
                 so.parent_mode = BFS_PARENT_MIN;
@@ -199,9 +211,13 @@ struct bfs_server {
                 st = bfs_run_multi(graphs[gid], srcs.data(), k, &o.opts, parent, depth, chunk, ws_bytes, stream,
                                    nullptr);
             }
+            const bool span_b = span_a && hipEventRecord(ev_b, stream) == hipSuccess;
             // the batch's memory goes back to the pool only once every kernel
             // that touches it has finished
             if (hipStreamSynchronize(stream) != hipSuccess && st == BFS_OK) st = BFS_E_HIP;
+            float ms_a = 0.f, ms_b = 0.f;
+            const bool span = st == BFS_OK && span_b && hipEventElapsedTime(&ms_a, ref_ev, ev_a) == hipSuccess &&
+                              hipEventElapsedTime(&ms_b, ref_ev, ev_b) == hipSuccess;
             if (st == BFS_OK) {
                 bool copied = false;
                 for (int j = 0; j < k; ++j) {
@@ -229,6 +245,7 @@ struct bfs_server {
                     if (first_error == BFS_OK) first_error = st;
                 }
                 --inflight;
+                if (span) dev_spans.emplace_back((double)ms_a, (double)ms_b);
                 last_completion = std::max(last_completion, t_done);
                 pool.release(off, bytes);
             }
@@ -236,6 +253,8 @@ struct bfs_server {
             cv_work.notify_all();
             cv_done.notify_all();
         }
+        (void)hipEventDestroy(ev_a);
+        (void)hipEventDestroy(ev_b);
         (void)hipStreamDestroy(stream);
     }
 
@@ -287,6 +306,14 @@ bfs_status bfs_server_create(const bfs_server_opts* o, bfs_server** out) {
         return BFS_E_HIP;
     }
     s->pool.init((char*)base, o->hbm_budget);
+    if (hipEventCreate(&s->ref_ev) != hipSuccess || hipEventRecord(s->ref_ev, nullptr) != hipSuccess ||
+        hipEventSynchronize(s->ref_ev) != hipSuccess) {
+        bfsk::set_last_error("server reference event");
+        if (s->ref_ev) (void)hipEventDestroy(s->ref_ev);
+        (void)hipFree(base);
+        delete s;
+        return BFS_E_HIP;
+    }
     for (int i = 0; i < o->slots; ++i) s->workers.emplace_back([s] { s->worker(); });
     *out = s;
     return BFS_OK;
@@ -395,6 +422,20 @@ bfs_status bfs_server_stats_get(bfs_server* s, bfs_server_stats* out) {
     out->last_completion_s = s->last_completion;
     const double span = s->last_completion - s->first_arrival;
     out->queries_per_s = span > 0 ? (double)(s->completed - s->failed) / span : 0.0;
+    // most device spans open at one time (a span that ends where another
+    // starts does not overlap it)
+    std::vector<std::pair<double, int>> ends;
+    ends.reserve(2 * s->dev_spans.size());
+    for (const auto& sp : s->dev_spans) {
+        ends.emplace_back(sp.first, 1);
+        ends.emplace_back(sp.second, -1);
+    }
+    std::sort(ends.begin(), ends.end());
+    int64_t open = 0;
+    for (const auto& e : ends) {
+        open += e.second;
+        out->device_max_overlap = std::max(out->device_max_overlap, open);
+    }
     return BFS_OK;
 }
 
@@ -423,6 +464,7 @@ void bfs_server_destroy(bfs_server* s) {
     s->cv_work.notify_all();
     for (auto& t : s->workers) t.join();
     for (auto& t : s->replayers) t.join();
+    if (s->ref_ev) (void)hipEventDestroy(s->ref_ev);
     if (s->pool.base) {
         const hipError_t e = hipFree(s->pool.base);
         if (e != hipSuccess) {

@@ -21,7 +21,7 @@ class bfs_server_stats(ctypes.Structure):
                 ("max_inflight", ctypes.c_int64), ("mean_batch", ctypes.c_double), ("p50_us", ctypes.c_double),
                 ("p99_us", ctypes.c_double), ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double),
                 ("first_arrival_s", ctypes.c_double), ("last_completion_s", ctypes.c_double),
-                ("queries_per_s", ctypes.c_double)]
+                ("queries_per_s", ctypes.c_double), ("device_max_overlap", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

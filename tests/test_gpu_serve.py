@@ -90,6 +90,8 @@ def test_tight_budget_queues_and_loses_nothing():
     reqs = [(0, int(s)) for s in graphgen.random_sources(big[0][0], 40, seed=1)]
     outs, st, (ids, lat, bsz, seq) = run_mix(big, reqs, slots=4, max_batch=64, want_parent=1, hbm_budget=one)
     assert st["completed"] == 40 and st["max_inflight"] == 1 and st["batches"] == 40
+    # one batch at a time: their spans on the device do not overlap either
+    assert st["device_max_overlap"] == 1
     for gi, s, p, d in outs:
         ap, ad = alone(big[gi], s)
         assert np.array_equal(d, ad) and np.array_equal(p, ap)
@@ -114,6 +116,9 @@ def test_batches_overlap_on_several_slots():
     st = srv.bfs_server_stats_get()
     srv.bfs_server_destroy()
     assert st["completed"] == rid and st["max_inflight"] > 1
+    # overlap seen on the device: HIP events around each batch on its slot's
+    # stream give spans of which several are open at once
+    assert st["device_max_overlap"] > 1
 
 
 def test_replay_poisson_stream():
