@@ -67,3 +67,39 @@ def test_host_argument_errors_need_no_gpu():
     assert lib.bfs_workspace_bytes(None, 1) == 0
     assert lib.bfs_create_graph_dcsc(0, 4, 0, 0, 0, None, None, None, 0, None, None, None, 0, 0, None,
                                      ctypes.byref(h)) == 1
+
+
+def test_binding_structs_match_the_headers(tmp_path):
+    """The Python binding's ctypes structures have the sizes and field offsets
+    that the C headers give them (checked with gcc; no GPU)."""
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    import paper_1705_04590_amd as bfs
+    from paper_1705_04590_amd import serve
+
+    structs = {"bfs_opts": bfs.bfs_opts, "bfs_stats": bfs.bfs_stats,
+               "bfs_server_opts": serve.bfs_server_opts, "bfs_server_stats": serve.bfs_server_stats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bfs_serve.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} . %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c11", "-Wall", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    for name, cls in structs.items():
+        assert got[(name, ".")] == ctypes.sizeof(cls), f"sizeof({name})"
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, f"offsetof({name}, {field})"
