@@ -399,6 +399,35 @@ def test_fused_search_selection(orc, graphs):
     assert st.launches[FUSED] == 1
 
 
+@pytest.mark.parametrize("name", ["kron12", "kron14", "er"])
+def test_deferred_depths_reach_the_hub_prepass(orc, graphs, name):
+    """Any-parent fetch-or searches leave a top-down level's depths to the next
+    level until the outputs are filled. Here the next level is a top-down level
+    heavy enough for the hub pre-pass, whose fill must write them: top-down
+    only (alpha ~ 0), engine off, and a pre-pass threshold that the first
+    level with more frontier edges than the level before reaches."""
+    for off_dtype in (np.int32, np.int64):
+        dg = get(graphs, name, off_dtype)
+        for s in sources_for(dg.off, k=2, seed=51)[:2]:
+            ref = orc.bfs_min(dg.off, dg.cols, int(s))
+            n_f, m_f, _ = orc.level_stats(dg.off, ref[1])
+            # the heaviest level, when some top-down level with edges runs
+            # before it: the levels before leave their depths to the next one
+            # (through the queue), and its pre-pass is the first to fill
+            grow = [lv for lv in range(1, len(m_f)) if m_f[lv - 1] > 0 and m_f[lv] > m_f[:lv].max()]
+            if not grow:
+                continue
+            lv = grow[-1]
+            p, d, st = dg.run(s, alpha=1e-9, small_edges=-1, td_prepass=int(m_f[lv]))
+            check(orc, dg, s, p, d, False, ref)
+            assert st.bu_levels == 0 and st.fill_level == lv
+            # and with no pre-pass at all: every level's depths come from the
+            # next level's queue, and a pass after the last level fills the -1
+            p, d, st = dg.run(s, alpha=1e-9, small_edges=-1, td_prepass=-1)
+            check(orc, dg, s, p, d, False, ref)
+            assert st.bu_levels == 0 and st.fill_level == -2
+
+
 @pytest.mark.parametrize("name", ["kron12", "pieces", "grid", "path"])
 def test_outputs_fully_written(orc, graphs, name):
     """Every parent/depth entry is written by the call, whatever the level
