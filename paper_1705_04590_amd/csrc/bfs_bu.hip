@@ -406,6 +406,9 @@ __global__ __launch_bounds__(BLK, 5) void k_bu_sweep(BFS_SWEEP_PARAMS) {
 // at a time (k_bu_sweep's second pass), so a step does not wait for one
 // lane's chain of offset, column and probe loads.  A hit found there is
 // written over the entry's -1.  Counts and bitmaps as k_bu_sweep.
+// HUB = 3 is the hub pre-pass of a heavy top-down level that writes the
+// outputs (k_td_hub_prepass's probes): no rows are scanned and only visited
+// changes.
 constexpr int BF_WORDS = 8;
 
 // lane j's value of x (j the same in every lane), as a wave-uniform value
@@ -499,7 +502,9 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_fill(
     const int64_t G = (W + BF_WORDS - 1) / BF_WORDS;
     const int64_t nwaves = (int64_t)gridDim.x * (BU_BLOCK / WAVE);
     uint64_t my_n = 0, my_m = 0, my_x = 0;
-    // entries the head probes; with HUB = 2 its last word holds hub ranks
+    // HUB = 3: the hub pre-pass of a heavy top-down level
+    constexpr bool PRE = HUB == 3;
+    // entries the head probes; with HUB >= 2 its last word holds hub ranks
     constexpr int32_t nprobe = HUB >= 2 ? 2 : 3;
     // a row scan starts past the head when the head is the row's prefix;
     // positions count the head's probes too when it is not
@@ -613,7 +618,8 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_fill(
             }
             const bool found = par >= 0;
             // the head did not settle v and its row goes on: the scan waits
-            const bool cont = act[j] && !found && deg > nprobe;
+            // (the pre-pass scans no rows)
+            const bool cont = !PRE && act[j] && !found && deg > nprobe;
             const uint64_t cm = __ballot(cont);
             if (cont) miss[nmiss + __popcll(cm & lanemask_lt())] = (int32_t)v;
             nmiss += __popcll(cm);
@@ -622,7 +628,7 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_fill(
                 my_m += (uint64_t)deg;
                 my_x += (uint64_t)(pos + 1);
             } else if (act[j] && !cont) {
-                my_x += (uint64_t)deg;
+                my_x += (uint64_t)(deg > nprobe ? pbase + deg : deg);
             }
             // every entry of a vertex not reached before this level, once
             // (isolated vertices are marked visited when a search starts)
@@ -635,7 +641,10 @@ __global__ __launch_bounds__(BU_BLOCK) void k_bu_fill(
                 depth[v] = next_depth - 1;
             }
             const uint64_t nb = __ballot(found);
-            if (lane == 0 && w < W) {
+            if (PRE) {
+                // the level's merge finds the hits as new (visited & ~vprev)
+                if (lane == 0 && w < W && nb) visited[w] = vw[j] | nb;
+            } else if (lane == 0 && w < W) {
                 nbits[w] = nb;
                 if (nb) {
                     visited[w] = vw[j] | nb;
@@ -846,17 +855,19 @@ void launch_bu_sweep(const Launch& L, const int4* head, int hub, const uint64_t*
     if (blk == 128) { BFS_SWEEP_H(F, 0, 128) }            \
     else if (blk == 512) { BFS_SWEEP_H(F, 0, 512) }       \
     else { BFS_SWEEP_H(F, 0, BU_BLOCK) }
-    if (fill && (hub == 1 || hub == 2) && !pend) {
-        // the first sweep of a search that writes the outputs, with heads of
-        // high-degree neighbours: one lane per vertex.  Heads that are row
-        // prefixes (HUB = 0) leave far more rows to scan (about one vertex in
-        // five on a large level), and k_bu_sweep's compacted lists do better.
+    if (fill && hub != 0 && !pend) {
+        // the first sweep of a search that writes the outputs (or the hub
+        // pre-pass that writes them), with heads of high-degree neighbours:
+        // one lane per vertex.  Heads that are row prefixes (HUB = 0) leave
+        // far more rows to scan (about one vertex in five on a large level),
+        // and k_bu_sweep's compacted lists do better.
         const int gf = grid_for((W + BF_WORDS - 1) / BF_WORDS, BU_BLOCK / WAVE, L.grid_cap);
 #define BFS_FILL1(H)                                                                                             \
     hipLaunchKernelGGL((k_bu_fill<OffT, H>), dim3(gf), dim3(BU_BLOCK), 0, L.stream, head, iso, nbase, off, cols, \
                        fbits, hb, nbits, visited, vprev, parent, depth, W, next_depth, serial_len, slot, zslot, n,   \
                        src, (int)frontier_depth)
-        if (hub == 2) BFS_FILL1(2);
+        if (hub == 3) BFS_FILL1(3);
+        else if (hub == 2) BFS_FILL1(2);
         else BFS_FILL1(1);
 #undef BFS_FILL1
         return;
